@@ -1,0 +1,383 @@
+"""FP64 CPU reference oracle for linear-time Sinkhorn divergences with
+positive features (Scetbon & Cuturi, "Linear Time Sinkhorn Divergences
+using Positive Features").
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this module: it exists so that tests, the smoke check and the CPU
+baseline of the benchmark can compare the GPU library against a plain,
+slow, obviously correct implementation.  It shares no code with the HIP
+library and does not import it.
+
+Everything is float64 NumPy.  Inputs given as float32 arrays are upcast, so
+both sides see the same numbers.  No blocking, fusion or reordering beyond
+what the definitions state.
+
+Pins (tests/test_oracle_pins.py, run without a GPU):
+  * lambert_q                - the defining identity of W0 (closed form).
+  * gaussian_log_features    - Gauss-Hermite quadrature of the integral
+                               representation of the Gaussian kernel
+                               (Lemma 1); convergence of K_theta to the
+                               Gaussian kernel as r grows (Prop. 3.1).
+  * sinkhorn                 - marginals, u^T K v = 1, brute-force dual
+                               maximisation, 2x2 primal bisection,
+                               primal/dual equality.
+  * w_hat / divergence       - translation closed form for the exact
+                               Gaussian kernel, symmetry, permutation.
+  * divergence_grad          - central finite differences; large-r limit
+                               of the squared-Euclidean Sinkhorn gradient.
+No function here is "parity unpinned".
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Optional
+
+import numpy as np
+from scipy.special import lambertw
+
+__all__ = [
+    "lambert_q", "sigma2_from_q", "q_from_sigma2",
+    "gaussian_log_features", "gaussian_features", "gaussian_features_scaled",
+    "gaussian_kernel", "rf_kernel",
+    "SinkhornResult", "sinkhorn", "sinkhorn_dense", "sinkhorn_factored",
+    "w_hat", "w_hat_scaled", "Divergence", "divergence",
+    "divergence_scaled", "divergence_from_kernels",
+    "primal_objective", "divergence_grad", "grad_x_exact_kernel",
+]
+
+F64 = np.float64
+
+
+# --------------------------------------------------------------------------
+# Bandwidth of the Gaussian feature map (Lemma 1, Sec. 3.2; proof in App. A)
+# --------------------------------------------------------------------------
+def lambert_q(R: float, eps: float, d: int) -> float:
+    """q = R^2 / (2 eps d W0(R^2 / (eps d))), W0 the principal real branch
+    of the Lambert function (Lemma 1, for points in the ball B(0, R))."""
+    z = (R * R) / (eps * d)
+    w = float(lambertw(z, 0).real)
+    return (R * R) / (2.0 * eps * d * w)
+
+
+def sigma2_from_q(q: float, eps: float) -> float:
+    """Anchor variance sigma^2 = q eps / 4 (Lemma 1)."""
+    return q * eps / 4.0
+
+
+def q_from_sigma2(sigma2: float, eps: float) -> float:
+    """Inverse of sigma2_from_q, for workloads that fix sigma^2 directly."""
+    return 4.0 * sigma2 / eps
+
+
+# --------------------------------------------------------------------------
+# Positive features for the Gaussian kernel k(x,y) = exp(-||x-y||^2/eps)
+# --------------------------------------------------------------------------
+def gaussian_log_features(X, U, eps: float, q: float,
+                          chunk: int = 4096) -> np.ndarray:
+    """log phi_theta(x_i)_k for the Gaussian feature map.
+
+    The per-anchor map (Lemma 1, in the form derived in its proof, App. A):
+        phi(x, u) = (2q)^{d/4} exp(-2||x - u||^2 / eps) exp(||u||^2 / (eps q))
+    and the finite feature vector of Eq. (general), Sec. 3.2:
+        phi_theta(x) = r^{-1/2} (phi(x, u_1), ..., phi(x, u_r)).
+    Squared distances are taken as direct differences.  Returns (n, r).
+    """
+    X = np.asarray(X, F64)
+    U = np.asarray(U, F64)
+    n, d = X.shape
+    r = U.shape[0]
+    const = -0.5 * math.log(r) + 0.25 * d * math.log(2.0 * q)
+    unorm = (U * U).sum(1) / (eps * q)
+    out = np.empty((n, r), F64)
+    for s in range(0, n, chunk):
+        diff = X[s:s + chunk, None, :] - U[None, :, :]
+        d2 = (diff * diff).sum(-1)
+        out[s:s + chunk] = const - (2.0 / eps) * d2 + unorm[None, :]
+    return out
+
+
+def gaussian_features(X, U, eps: float, q: float) -> np.ndarray:
+    """Features phi_theta(x_i) as rows, (n, r); K_theta = Phi_x Phi_y^T."""
+    return np.exp(gaussian_log_features(X, U, eps, q))
+
+
+def gaussian_features_scaled(X, U, eps: float, q: float):
+    """Row-scaled features: Phi = diag(exp(s)) Phi_tilde with
+    s_i = max_k log phi_theta(x_i)_k, so every entry of Phi_tilde lies in
+    (0, 1].  The scaling is absorbed exactly by the Sinkhorn scalings
+    (u_tilde = u * exp(s)); it is not in the paper and only keeps the
+    entries representable.  Returns (Phi_tilde (n, r), s (n,))."""
+    E = gaussian_log_features(X, U, eps, q)
+    s = E.max(axis=1)
+    return np.exp(E - s[:, None]), s
+
+
+def gaussian_kernel(X, Y, eps: float) -> np.ndarray:
+    """Exact Gibbs kernel of the squared Euclidean cost, exp(-||x-y||^2/eps)."""
+    X = np.asarray(X, F64)
+    Y = np.asarray(Y, F64)
+    diff = X[:, None, :] - Y[None, :, :]
+    return np.exp(-(diff * diff).sum(-1) / eps)
+
+
+def rf_kernel(X, Y, U, eps: float, q: float) -> np.ndarray:
+    """K_theta = Xi^T Zeta = Phi_x Phi_y^T (Sec. 3.1)."""
+    return gaussian_features(X, U, eps, q) @ gaussian_features(Y, U, eps, q).T
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1 (Sinkhorn), Sec. 2
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class SinkhornResult:
+    u: np.ndarray          # row scaling
+    v: np.ndarray          # column scaling
+    iters: int             # number of (v-update, u-update) pairs done
+    err: float             # ||v o K^T u - b||_1 after the last u-update
+    converged: bool
+
+
+def sinkhorn(apply_K: Callable, apply_Kt: Callable, a, b, tol: float = 1e-6,
+             max_iter: int = 2000, fixed_iter: int = 0,
+             u0: Optional[np.ndarray] = None) -> SinkhornResult:
+    """Algorithm 1: starting from a positive u, repeat
+           v <- b / K^T u,   u <- a / K v
+    until ||v o K^T u - b||_1 < tol (tested after each u-update).
+
+    ``apply_K(v) = K v`` and ``apply_Kt(u) = K^T u``.  With ``fixed_iter``
+    > 0 exactly that many iterations are done and the error is only
+    reported.  Otherwise at most ``max_iter`` iterations are done.
+    """
+    a = np.asarray(a, F64)
+    b = np.asarray(b, F64)
+    u = np.ones_like(a) if u0 is None else np.asarray(u0, F64).copy()
+    Ktu = apply_Kt(u)
+    limit = fixed_iter if fixed_iter > 0 else max_iter
+    err = math.inf
+    v = None
+    k = 0
+    converged = False
+    for k in range(1, limit + 1):
+        v = b / Ktu
+        u = a / apply_K(v)
+        Ktu = apply_Kt(u)
+        err = float(np.abs(v * Ktu - b).sum())
+        if fixed_iter <= 0 and err < tol:
+            converged = True
+            break
+    if fixed_iter > 0:
+        converged = err < tol
+    return SinkhornResult(u, v, k, err, converged)
+
+
+def sinkhorn_dense(K, a, b, **kw) -> SinkhornResult:
+    """Algorithm 1 on a materialised n x m kernel matrix."""
+    K = np.asarray(K, F64)
+    return sinkhorn(lambda v: K @ v, lambda u: K.T @ u, a, b, **kw)
+
+
+def sinkhorn_factored(Phix, Phiy, a, b, **kw) -> SinkhornResult:
+    """Algorithm 1 on K = Phix Phiy^T applied as two skinny products, the
+    r(n+m) form of Sec. 3.1."""
+    Phix = np.asarray(Phix, F64)
+    Phiy = np.asarray(Phiy, F64)
+    return sinkhorn(lambda v: Phix @ (Phiy.T @ v),
+                    lambda u: Phiy @ (Phix.T @ u), a, b, **kw)
+
+
+def w_hat(u, v, a, b, eps: float) -> float:
+    """Dual estimate eps (a^T log u + b^T log v) of Eq. (dual-estimate),
+    Sec. 2 (valid because u^T K v = 1 after any Sinkhorn update)."""
+    a = np.asarray(a, F64)
+    b = np.asarray(b, F64)
+    return float(eps * (a @ np.log(u) + b @ np.log(v)))
+
+
+def primal_objective(P, K, eps: float) -> float:
+    """<P, C> - eps H(P) + eps with C = -eps log K and
+    H(P) = -sum P (log P - 1), Eq. (reg-ot), Sec. 2."""
+    P = np.asarray(P, F64)
+    C = -eps * np.log(np.asarray(K, F64))
+    H = -(P * (np.log(P) - 1.0)).sum()
+    return float((P * C).sum() - eps * H + eps)
+
+
+# --------------------------------------------------------------------------
+# Sinkhorn divergence, Eq. (reg-sdiv), Sec. 2
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class Divergence:
+    value: float           # W_bar = W(mu,nu) - (W(mu,mu) + W(nu,nu)) / 2
+    w_xy: float
+    w_xx: float
+    w_yy: float
+    xy: SinkhornResult
+    xx: SinkhornResult
+    yy: SinkhornResult
+
+
+def divergence_from_kernels(Kxy, Kxx, Kyy, a, b, eps, **kw) -> Divergence:
+    """Debiased divergence from three dense kernels: three runs of
+    Algorithm 1 and their dual estimates (Eq. reg-sdiv, Eq. dual-estimate)."""
+    xy = sinkhorn_dense(Kxy, a, b, **kw)
+    xx = sinkhorn_dense(Kxx, a, a, **kw)
+    yy = sinkhorn_dense(Kyy, b, b, **kw)
+    wxy = w_hat(xy.u, xy.v, a, b, eps)
+    wxx = w_hat(xx.u, xx.v, a, a, eps)
+    wyy = w_hat(yy.u, yy.v, b, b, eps)
+    return Divergence(wxy - 0.5 * (wxx + wyy), wxy, wxx, wyy, xy, xx, yy)
+
+
+def divergence(X, Y, a, b, U, eps: float, q: float, tol: float = 1e-6,
+               max_iter: int = 2000, fixed_iter: int = 0,
+               dense: Optional[bool] = None) -> Divergence:
+    """Sinkhorn divergence with the positive-feature kernel K_theta.
+
+    Each of the three problems (x,y), (x,x), (y,y) runs Algorithm 1 from
+    u0 = exp(-s_x) (a positive start, allowed by Sec. 2), where s_x is the
+    per-point maximum log-feature.  Dense K_theta when n*m is small
+    (``dense=None`` picks dense for n*m <= 4e7), otherwise the factored
+    product.  The unscaled features are used, so this is plain Algorithm 1
+    on K_theta; it needs exp(log-features) representable in float64.
+    """
+    Ex = gaussian_log_features(X, U, eps, q)
+    Ey = gaussian_log_features(Y, U, eps, q)
+    sx = Ex.max(1)
+    sy = Ey.max(1)
+    Px, Py = np.exp(Ex), np.exp(Ey)
+    n, m = Px.shape[0], Py.shape[0]
+    if dense is None:
+        dense = n * m <= 4e7 and n * n <= 4e7 and m * m <= 4e7
+    kw = dict(tol=tol, max_iter=max_iter, fixed_iter=fixed_iter)
+    if dense:
+        def run(A, B, wa, wb, s0):
+            return sinkhorn_dense(A @ B.T, wa, wb, u0=np.exp(-s0), **kw)
+    else:
+        def run(A, B, wa, wb, s0):
+            return sinkhorn_factored(A, B, wa, wb, u0=np.exp(-s0), **kw)
+    xy = run(Px, Py, a, b, sx)
+    xx = run(Px, Px, a, a, sx)
+    yy = run(Py, Py, b, b, sy)
+    wxy = w_hat(xy.u, xy.v, a, b, eps)
+    wxx = w_hat(xx.u, xx.v, a, a, eps)
+    wyy = w_hat(yy.u, yy.v, b, b, eps)
+    return Divergence(wxy - 0.5 * (wxx + wyy), wxy, wxx, wyy, xy, xx, yy)
+
+
+def w_hat_scaled(ut, vt, a, b, sx, sy, eps: float) -> float:
+    """Dual estimate for the row-scaled problem.  With Phi = diag(e^s) Phi~,
+    the scalings of K_theta are u = u~ e^{-s_x}, v = v~ e^{-s_y}, so
+    eps(a^T log u + b^T log v) = eps(a^T log u~ + b^T log v~)
+                                 - eps(a^T s_x + b^T s_y)."""
+    a = np.asarray(a, F64)
+    b = np.asarray(b, F64)
+    return float(eps * (a @ np.log(ut) + b @ np.log(vt))
+                 - eps * (a @ np.asarray(sx, F64) + b @ np.asarray(sy, F64)))
+
+
+def divergence_scaled(X, Y, a, b, U, eps: float, q: float, tol: float = 1e-6,
+                      max_iter: int = 2000, fixed_iter: int = 0,
+                      dense: Optional[bool] = None) -> Divergence:
+    """Same quantity as ``divergence`` computed on the row-scaled features:
+    Algorithm 1 on K~ = Phi~_x Phi~_y^T from u~0 = 1 (the image of
+    u0 = exp(-s_x) under the scaling), then ``w_hat_scaled``.  The iterates
+    are those of ``divergence`` times exp(s); unlike ``divergence`` it
+    never forms exp of a raw log-feature, so it also covers workloads whose
+    raw features underflow float64 (small eps, large d).  The returned
+    SinkhornResult scalings are the scaled ones (u~, v~)."""
+    Px, sx = gaussian_features_scaled(X, U, eps, q)
+    Py, sy = gaussian_features_scaled(Y, U, eps, q)
+    n, m = Px.shape[0], Py.shape[0]
+    if dense is None:
+        dense = n * m <= 4e7 and n * n <= 4e7 and m * m <= 4e7
+    kw = dict(tol=tol, max_iter=max_iter, fixed_iter=fixed_iter)
+    if dense:
+        def run(A, B, wa, wb):
+            return sinkhorn_dense(A @ B.T, wa, wb, **kw)
+    else:
+        def run(A, B, wa, wb):
+            return sinkhorn_factored(A, B, wa, wb, **kw)
+    xy = run(Px, Py, a, b)
+    xx = run(Px, Px, a, a)
+    yy = run(Py, Py, b, b)
+    wxy = w_hat_scaled(xy.u, xy.v, a, b, sx, sy, eps)
+    wxx = w_hat_scaled(xx.u, xx.v, a, a, sx, sx, eps)
+    wyy = w_hat_scaled(yy.u, yy.v, b, b, sy, sy, eps)
+    return Divergence(wxy - 0.5 * (wxx + wyy), wxy, wxx, wyy, xy, xx, yy)
+
+
+# --------------------------------------------------------------------------
+# Gradients (Prop. 3.2 and the chain rule that follows it, Sec. 3.3)
+# --------------------------------------------------------------------------
+def _grad_points_one_side(Xs, U, eps, Phi, p, g):
+    """Gradient of W_hat with respect to the points of one side.
+
+    Prop. 3.2 gives dW/dK = -eps u v^T at the optimum.  With
+    K_ij = sum_k phi_k(x_i) phi_k(y_j) and, from the feature map,
+    d phi_k(x)/dx = -(4/eps)(x - u_k) phi_k(x), the chain rule gives for a
+    point on the row side (p = u, g = Phi_y^T v):
+        dW/dx_i = 4 p_i sum_k phi_k(x_i) g_k (x_i - u_k).
+    The same expression with p = v, g = Phi_x^T u holds for the column side.
+    """
+    Xs = np.asarray(Xs, F64)
+    U = np.asarray(U, F64)
+    wphi = Phi * g[None, :]                      # phi_k(x_i) g_k
+    term1 = wphi.sum(1)[:, None] * Xs            # sum_k phi g  x_i
+    term2 = wphi @ U                             # sum_k phi g  u_k
+    return 4.0 * p[:, None] * (term1 - term2)
+
+
+def divergence_grad(X, Y, a, b, U, eps: float, q: float, tol: float = 1e-13,
+                    max_iter: int = 100000, fixed_iter: int = 0):
+    """Gradients of the divergence with respect to X, a, Y, b.
+
+    Point gradients: the envelope gradient of Prop. 3.2 pushed through the
+    feature map (the gradient formula with respect to the point locations
+    in Sec. 3.3).  A point of X enters W(mu, nu) on the row side and
+    W(mu, mu) on both sides, so
+        dW_bar/dX = G_row(xy) - (G_row(xx) + G_col(xx)) / 2.
+    Weight gradients: by the envelope theorem on Eq. (eval-dual),
+    dW/da = alpha* = eps log u (row side) and eps log v (column side); the
+    dual optimum is unique only up to a constant shift (App. B), so the
+    gradient is returned centred (mean removed), i.e. projected on the
+    tangent space {sum da = 0} of the simplex.
+    Returns (dX, da, dY, db, Divergence).
+    """
+    Phx = gaussian_features(X, U, eps, q)
+    Phy = gaussian_features(Y, U, eps, q)
+    sx = gaussian_log_features(X, U, eps, q).max(1)
+    sy = gaussian_log_features(Y, U, eps, q).max(1)
+    kw = dict(tol=tol, max_iter=max_iter, fixed_iter=fixed_iter)
+    xy = sinkhorn_dense(Phx @ Phy.T, a, b, u0=np.exp(-sx), **kw)
+    xx = sinkhorn_dense(Phx @ Phx.T, a, a, u0=np.exp(-sx), **kw)
+    yy = sinkhorn_dense(Phy @ Phy.T, b, b, u0=np.exp(-sy), **kw)
+    wxy = w_hat(xy.u, xy.v, a, b, eps)
+    wxx = w_hat(xx.u, xx.v, a, a, eps)
+    wyy = w_hat(yy.u, yy.v, b, b, eps)
+    div = Divergence(wxy - 0.5 * (wxx + wyy), wxy, wxx, wyy, xy, xx, yy)
+
+    dX = (_grad_points_one_side(X, U, eps, Phx, xy.u, Phy.T @ xy.v)
+          - 0.5 * (_grad_points_one_side(X, U, eps, Phx, xx.u, Phx.T @ xx.v)
+                   + _grad_points_one_side(X, U, eps, Phx, xx.v, Phx.T @ xx.u)))
+    dY = (_grad_points_one_side(Y, U, eps, Phy, xy.v, Phx.T @ xy.u)
+          - 0.5 * (_grad_points_one_side(Y, U, eps, Phy, yy.u, Phy.T @ yy.v)
+                   + _grad_points_one_side(Y, U, eps, Phy, yy.v, Phy.T @ yy.u)))
+    da = eps * (np.log(xy.u) - 0.5 * (np.log(xx.u) + np.log(xx.v)))
+    db = eps * (np.log(xy.v) - 0.5 * (np.log(yy.u) + np.log(yy.v)))
+    da = da - da.mean()
+    db = db - db.mean()
+    return dX, da, dY, db, div
+
+
+def grad_x_exact_kernel(X, Y, a, b, eps: float, tol: float = 1e-13,
+                        max_iter: int = 100000):
+    """Gradient of W(mu, nu) in X for the exact squared-Euclidean cost:
+    dW/dx_i = sum_j P_ij 2 (x_i - y_j) = 2 (a_i x_i - sum_j P_ij y_j),
+    P the optimal plan.  The limit r -> infinity of the feature gradient."""
+    X = np.asarray(X, F64)
+    Y = np.asarray(Y, F64)
+    K = gaussian_kernel(X, Y, eps)
+    res = sinkhorn_dense(K, a, b, tol=tol, max_iter=max_iter)
+    P = res.u[:, None] * K * res.v[None, :]
+    return 2.0 * (P.sum(1)[:, None] * X - P @ Y)
