@@ -1,0 +1,254 @@
+/*
+ * sinkhorn.h - C ABI of the MI355X (gfx950) library for linear-time Sinkhorn
+ * divergences with positive features (Scetbon & Cuturi, "Linear Time
+ * Sinkhorn Divergences using Positive Features").
+ *
+ * The library computes, for two discrete measures mu = sum_i a_i delta_{x_i}
+ * and nu = sum_j b_j delta_{y_j} (Sec. 2, Eq. reg-sdiv / reg-ot):
+ *   1. positive Gaussian features phi_theta (Lemma 1, Sec. 3.2; Eq. general)
+ *      so that K_theta = Phi_x Phi_y^T (Sec. 3.1),
+ *   2. the Sinkhorn scalings (u, v) of Algorithm 1 (Sec. 2) applied to the
+ *      factored kernel in r(n+m) operations per iteration (Sec. 3.1),
+ *   3. the L1 marginal-error stopping test of Algorithm 1,
+ *   4. the dual estimate eps (a^T log u + b^T log v) (Eq. dual-estimate) and
+ *      the debiased divergence W(mu,nu) - (W(mu,mu) + W(nu,nu)) / 2,
+ *   5. gradients with respect to point locations and weights through the
+ *      envelope gradient -eps u v^T of Prop. 3.2 and the chain rule of
+ *      Sec. 3.3.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named without a _host suffix are DEVICE pointers (memory of
+ *     the current HIP device, e.g. from hipMalloc or a torch CUDA tensor).
+ *     All device buffers are owned by the caller; the library never
+ *     allocates device memory inside these calls and never frees caller
+ *     memory.
+ *   - Matrices are row-major and contiguous: X is n x d (row i = x_i),
+ *     U is r x d (row k = anchor u_k), Phi is n x r (row i = phi(x_i)).
+ *   - Floating point arrays are float32 unless named otherwise; results of
+ *     the final reductions are float64.
+ *   - Calls are asynchronous and stream-ordered on `stream` (a hipStream_t;
+ *     NULL means the default stream).  Argument errors are detected on the
+ *     host before anything is enqueued and returned synchronously; numerical
+ *     outcomes are written to device-resident sk_solve_info records and are
+ *     readable after the stream has been synchronised.
+ *   - Return value: SK_OK or one of the error codes below.  Nothing is
+ *     enqueued when a call returns an error.
+ *   - Concurrency: the solver launches persistent kernels whose workgroups
+ *     wait on each other.  Launches from this library must not overlap with
+ *     each other on different streams of the same device (use one stream);
+ *     every wait is bounded, and a wait that exceeds its bound ends the
+ *     launch with status SK_ETIMEOUT instead of hanging.
+ */
+#ifndef PAPER_2006_07057_AMD_SINKHORN_H
+#define PAPER_2006_07057_AMD_SINKHORN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* sk_stream_t; /* a hipStream_t */
+
+/* Status codes (returned, or written to sk_solve_info.status). */
+enum {
+  SK_OK = 0,
+  SK_EINVAL = 1,    /* invalid argument (size, pointer, eps, tol, weights) */
+  SK_ENOMEM = 2,    /* workspace or state buffer too small */
+  SK_ERANGE = 3,    /* a Sinkhorn division met a zero or non-finite value */
+  SK_ENOTCONV = 4,  /* max_iter reached before the tolerance */
+  SK_EHIP = 5,      /* a HIP runtime call failed */
+  SK_ETIMEOUT = 6,  /* a device-side wait exceeded its bound */
+  SK_ENOTSUP = 7    /* unsupported shape (see the entry point) */
+};
+
+/* Largest number of features per point supported by the solver. */
+#define SK_MAX_R 4096
+
+/* Options of Algorithm 1 (Sec. 2).
+ *   tol        stop after the first iteration whose column marginal error
+ *              ||v o K^T u - b||_1 (computed in float64) is below tol;
+ *   max_iter   at most this many iterations (one iteration = the v-update
+ *              followed by the u-update);
+ *   fixed_iter if > 0, exactly this many iterations and no stopping test
+ *              (the final error is still measured and reported);
+ *   warm_start if nonzero, the u buffer passed to sinkhorn_solve holds the
+ *              starting (positive) scaling; otherwise u starts at 1.  Any
+ *              positive start is allowed by Sec. 2. */
+typedef struct {
+  double tol;
+  int32_t max_iter;
+  int32_t fixed_iter;
+  int32_t warm_start;
+  int32_t reserved;
+} sk_solve_opts;
+
+/* Outcome of one run of Algorithm 1, written by the device.
+ *   iters     iterations whose (u, v) are returned;
+ *   status    SK_OK, SK_ENOTCONV, SK_ERANGE or SK_ETIMEOUT;
+ *   err       ||v o K^T u - b||_1 of the returned pair (float64);
+ *   w_hat     dual estimate eps (a^T log u + b^T log v) of Eq.
+ *             (dual-estimate) for the kernel the solver was given,
+ *             accumulated in float64 from the float32 scalings. */
+typedef struct {
+  int32_t iters;
+  int32_t status;
+  double err;
+  double w_hat;
+} sk_solve_info;
+
+/* ------------------------------------------------------------------ (a1) */
+/* Bandwidth of the Gaussian feature map, Lemma 1 (Sec. 3.2):
+ *   q = R^2 / (2 eps d W0(R^2 / (eps d))),  W0 = principal Lambert branch,
+ * for points in the ball of radius R.  Anchors are then drawn i.i.d. from
+ * N(0, sigma^2 I_d) with sigma^2 = q eps / 4.  Host-only; writes *q_host.
+ * SK_EINVAL if R <= 0, eps <= 0, d <= 0 or q_host is NULL. */
+int sinkhorn_gaussian_q(double R, double eps, int64_t d, double* q_host);
+
+/* ------------------------------------------------------------------ (a2) */
+/* Positive Gaussian features, row-scaled.  For each point x_i (row of X)
+ * and anchor u_k (row of U) the log-feature of Lemma 1 / Eq. (general) is
+ *   E_ik = -log(r)/2 + (d/4) log(2q) - (2/eps)||x_i - u_k||^2
+ *          + ||u_k||^2 / (eps q),
+ * so phi_theta(x_i)_k = exp(E_ik).  The call writes
+ *   logscale[i] = s_i = max_k E_ik            (n floats)
+ *   Phi[i*r+k]  = exp(E_ik - s_i) in (0, 1]   (n x r floats)
+ * i.e. Phi_theta = diag(exp(s)) Phi.  The factor exp(s) is absorbed exactly
+ * by the Sinkhorn scalings (u = u~ exp(-s)), which keeps every feature
+ * representable in float32.
+ * Arguments: X (n x d), U (r x d) device float32; eps > 0; q > 1/2;
+ * 1 <= r <= SK_MAX_R, d >= 1, n >= 1.  Phi and logscale must not overlap X
+ * or U.  Errors: SK_EINVAL for bad sizes/pointers/eps/q. */
+int sinkhorn_features(const float* X, int64_t n, int64_t d, const float* U,
+                      int64_t r, double eps, double q, float* Phi,
+                      float* logscale, sk_stream_t stream);
+
+/* ------------------------------------------------------------- (a3)(a4) */
+/* Workspace bytes needed by sinkhorn_solve for these sizes (host). */
+size_t sinkhorn_solve_workspace_size(int64_t n, int64_t m, int64_t r);
+
+/* Algorithm 1 on the factored kernel K = Phix Phiy^T (Sec. 3.1), each
+ * iteration v <- b / (Phiy (Phix^T u)), u <- a / (Phix (Phiy^T v)) done as
+ * two fused passes that read each feature row once, until the float64 L1
+ * column-marginal error drops below opts->tol (or per opts->fixed_iter).
+ * Inputs:  Phix (n x r), Phiy (m x r) positive features; a (n), b (m)
+ *          positive weights.  r % 4 == 0, r <= SK_MAX_R.
+ * Outputs: u (n), v (m) scalings; w = Phiy^T v (r), z = Phix^T u (r)
+ *          (the r-vectors the adjoint needs); *info (device).
+ *          u is read as the starting point when opts->warm_start != 0.
+ * ws:      device workspace of at least sinkhorn_solve_workspace_size bytes,
+ *          used as scratch (contents on entry are ignored).
+ * Errors:  SK_EINVAL (sizes, pointers, tol < 0, max_iter < 1),
+ *          SK_ENOMEM (ws too small), SK_ENOTSUP (r % 4 != 0 or r > 4096). */
+int sinkhorn_solve(const float* Phix, int64_t n, const float* Phiy, int64_t m,
+                   int64_t r, const float* a, const float* b,
+                   const sk_solve_opts* opts, float* u, float* v, float* w,
+                   float* z, sk_solve_info* info, void* ws, size_t ws_bytes,
+                   sk_stream_t stream);
+
+/* ------------------------------------------------------------------ (a5) */
+/* One divergence problem: points, weights and the feature map. */
+typedef struct {
+  const float* X;  /* n x d */
+  const float* Y;  /* m x d */
+  const float* a;  /* n, positive, sums to 1 */
+  const float* b;  /* m, positive, sums to 1 */
+  const float* U;  /* r x d anchors */
+  int64_t n, m, d, r;
+  double eps;      /* entropic regularisation, > 0 */
+  double q;        /* feature bandwidth parameter of Lemma 1, > 1/2 */
+} sk_problem;
+
+/* Byte offsets of the pieces of a divergence state buffer (all 256-byte
+ * aligned).  The state holds everything the backward pass needs, so the
+ * scaling loop never has to be replayed (Sec. 4, "Optimisation"). */
+typedef struct {
+  size_t phix, phiy;      /* float n x r, m x r   row-scaled features */
+  size_t sx, sy;          /* float n, m           row log-scales */
+  size_t u[3], v[3];      /* float scalings of the (x,y), (x,x), (y,y) solves */
+  size_t w[3], z[3];      /* float r: w = Phi_col^T v, z = Phi_row^T u */
+  size_t info;            /* sk_solve_info[3] */
+  size_t out;             /* double[4]: W_bar, W_xy, W_xx, W_yy */
+  size_t total;           /* total bytes */
+} sk_state_layout;
+
+/* Fill *layout for a problem of this size (host). */
+int sinkhorn_state_layout(int64_t n, int64_t m, int64_t r,
+                          sk_state_layout* layout);
+
+/* Workspace bytes for sinkhorn_divergence / _backward (host). */
+size_t sinkhorn_divergence_workspace_size(const sk_problem* p);
+
+/* Debiased Sinkhorn divergence of Eq. (reg-sdiv):
+ *   W_bar = W(mu,nu) - (W(mu,mu) + W(nu,nu)) / 2,
+ * each term the dual estimate (Eq. dual-estimate) of one run of Algorithm 1
+ * on K_theta.  Computes the features of X and Y, runs the three solves in
+ * one persistent launch and reduces in float64.
+ * out:   device double[4] = {W_bar, W_xy, W_xx, W_yy}.
+ * state: device buffer of sinkhorn_state_layout().total bytes; on return it
+ *        holds the features, scalings and infos (layout above).
+ * ws:    device workspace of sinkhorn_divergence_workspace_size bytes.
+ * Errors: SK_EINVAL, SK_ENOMEM, SK_ENOTSUP as for the calls it makes. */
+int sinkhorn_divergence(const sk_problem* p, const sk_solve_opts* opts,
+                        double* out, void* state, size_t state_bytes,
+                        void* ws, size_t ws_bytes, sk_stream_t stream);
+
+/* ------------------------------------------------------------------ (a6) */
+/* Workspace bytes for a batch of `count` problems (host). */
+size_t sinkhorn_batched_workspace_size(const sk_problem* problems,
+                                       int32_t count);
+
+/* `count` independent divergences (the mini-batch objective of Sec. 4 is
+ * an average of such terms).  problems: HOST array of count descriptors
+ * (their pointers are device pointers).  states: HOST array of count device
+ * state buffers, each sized by sinkhorn_state_layout for its problem.
+ * out: device double[4*count] (W_bar, W_xy, W_xx, W_yy per problem).
+ * Features of every problem are computed in batched launches, then all
+ * 3*count solves run in persistent launches that pack problems of uneven
+ * size (grouped by feature-count class), each solve on its own group of
+ * workgroups.  Results equal those of sinkhorn_divergence on each problem
+ * alone.  Errors as sinkhorn_divergence. */
+int sinkhorn_divergence_batched(const sk_problem* problems, int32_t count,
+                                const sk_solve_opts* opts, double* out,
+                                void* const* states, void* ws,
+                                size_t ws_bytes, sk_stream_t stream);
+
+/* ------------------------------------------------------------------ (a8) */
+/* Adjoint of the feature map for the envelope gradient (Prop. 3.2 and the
+ * point-location gradient of Sec. 3.3).  For one side of one solve with
+ * scaling p (n) and r-vector g (w for the row side, z for the column side):
+ *   dX[i] (+)= coef * 4 p_i ( x_i (Phi_i . g) - sum_k Phi_ik g_k u_k )
+ * with Phi the row-scaled features of X (so p is the matching scaled
+ * scaling).  accumulate != 0 adds to dX, otherwise overwrites it.
+ * Errors: SK_EINVAL. */
+int sinkhorn_features_backward(const float* X, int64_t n, int64_t d,
+                               const float* U, int64_t r, const float* Phi,
+                               const float* p, const float* g, float coef,
+                               int32_t accumulate, float* dX,
+                               sk_stream_t stream);
+
+/* Gradient of the divergence computed by sinkhorn_divergence (same problem
+ * and state) with respect to X, a, Y and b, scaled by *grad_out (a device
+ * float, NULL = 1):
+ *   dX = G_row(xy) - (G_row(xx) + G_col(xx)) / 2,   G from the call above;
+ *   da = eps (log u_xy - (log u_xx + log v_xx) / 2), centred (mean removed:
+ *        the dual optimum is unique only up to a constant, App. B);
+ * and symmetrically for dY, db.  Any of dX, da, dY, db may be NULL.
+ * ws: sinkhorn_divergence_workspace_size bytes.  Errors: SK_EINVAL. */
+int sinkhorn_divergence_backward(const sk_problem* p, const void* state,
+                                 const float* grad_out, float* dX, float* da,
+                                 float* dY, float* db, void* ws,
+                                 size_t ws_bytes, sk_stream_t stream);
+
+/* Human-readable name of a status code (static string). */
+const char* sinkhorn_strerror(int status);
+
+/* Library version string (static). */
+const char* sinkhorn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_2006_07057_AMD_SINKHORN_H */

@@ -1,0 +1,314 @@
+"""PyTorch-facing binding of the C ABI.
+
+Every function here only checks and marshals arguments (device pointers,
+sizes, the current HIP stream) and calls the HIP library; all arithmetic of
+the method runs in the library's kernels.  PyTorch provides device memory
+and streams.  Names follow the C ABI (sinkhorn_features, sinkhorn_solve,
+sinkhorn_divergence, ... ) with the ``sinkhorn_`` prefix dropped.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import lib, check, sk_problem, sk_solve_opts, sk_state_layout
+
+INFO_DTYPE = np.dtype([("iters", "<i4"), ("status", "<i4"), ("err", "<f8"),
+                       ("w_hat", "<f8")])
+INFO_BYTES = INFO_DTYPE.itemsize  # 24
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _need(t: torch.Tensor, name: str, dtype=torch.float32, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device (cuda) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
+    return t
+
+
+def _opts(tol=1e-6, max_iter=2000, fixed_iter=0, warm_start=False):
+    return sk_solve_opts(float(tol), int(max_iter), int(fixed_iter),
+                         int(bool(warm_start)), 0)
+
+
+def parse_infos(raw: torch.Tensor) -> np.ndarray:
+    """Decode device sk_solve_info records (synchronises)."""
+    return raw.detach().cpu().numpy().view(INFO_DTYPE)
+
+
+# ------------------------------------------------------------------ (a1)
+def gaussian_q(R: float, eps: float, d: int) -> float:
+    """Lemma 1 bandwidth q (host computation in the library)."""
+    q = ctypes.c_double()
+    check(lib().sinkhorn_gaussian_q(float(R), float(eps), int(d),
+                                    ctypes.byref(q)), "sinkhorn_gaussian_q")
+    return q.value
+
+
+# ------------------------------------------------------------------ (a2)
+def features(X: torch.Tensor, U: torch.Tensor, eps: float, q: float):
+    """Row-scaled Gaussian features: returns (Phi (n, r), s (n,)) with
+    phi_theta(x_i) = exp(s_i) Phi[i]."""
+    _need(X, "X")
+    _need(U, "U")
+    n, d = X.shape
+    r = U.shape[0]
+    if U.shape[1] != d:
+        raise ValueError("U must be r x d with the same d as X")
+    Phi = torch.empty((n, r), dtype=torch.float32, device=X.device)
+    s = torch.empty((n,), dtype=torch.float32, device=X.device)
+    check(lib().sinkhorn_features(_ptr(X), n, d, _ptr(U), r, float(eps),
+                                  float(q), _ptr(Phi), _ptr(s),
+                                  _stream(X.device)), "sinkhorn_features")
+    return Phi, s
+
+
+# -------------------------------------------------------------- (a3)(a4)
+@dataclasses.dataclass
+class SolveResult:
+    u: torch.Tensor
+    v: torch.Tensor
+    w: torch.Tensor
+    z: torch.Tensor
+    info_raw: torch.Tensor
+
+    def info(self):
+        return parse_infos(self.info_raw)[0]
+
+
+def solve(Phix: torch.Tensor, Phiy: torch.Tensor, a: torch.Tensor,
+          b: torch.Tensor, tol: float = 1e-6, max_iter: int = 2000,
+          fixed_iter: int = 0, u0: Optional[torch.Tensor] = None,
+          workspace: Optional[torch.Tensor] = None) -> SolveResult:
+    """Algorithm 1 on K = Phix Phiy^T (asynchronous; read .info() to sync)."""
+    _need(Phix, "Phix")
+    _need(Phiy, "Phiy")
+    n, r = Phix.shape
+    m = Phiy.shape[0]
+    if Phiy.shape[1] != r:
+        raise ValueError("Phix and Phiy need the same number of features")
+    _need(a, "a", shape=(n,))
+    _need(b, "b", shape=(m,))
+    dev = Phix.device
+    u = u0.clone() if u0 is not None else torch.empty(n, dtype=torch.float32, device=dev)
+    v = torch.empty(m, dtype=torch.float32, device=dev)
+    w = torch.empty(r, dtype=torch.float32, device=dev)
+    z = torch.empty(r, dtype=torch.float32, device=dev)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=dev)
+    need = lib().sinkhorn_solve_workspace_size(n, m, r)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    o = _opts(tol, max_iter, fixed_iter, u0 is not None)
+    check(lib().sinkhorn_solve(_ptr(Phix), n, _ptr(Phiy), m, r, _ptr(a), _ptr(b),
+                               ctypes.byref(o), _ptr(u), _ptr(v), _ptr(w),
+                               _ptr(z), _ptr(info), _ptr(workspace),
+                               workspace.numel(), _stream(dev)),
+          "sinkhorn_solve")
+    return SolveResult(u, v, w, z, info)
+
+
+# ------------------------------------------------------------------ (a5)
+def state_layout(n: int, m: int, r: int) -> sk_state_layout:
+    L = sk_state_layout()
+    check(lib().sinkhorn_state_layout(n, m, r, ctypes.byref(L)),
+          "sinkhorn_state_layout")
+    return L
+
+
+class DivergenceState:
+    """Device state of one divergence (features, scalings, infos), kept for
+    the backward pass and for inspection."""
+
+    def __init__(self, X, Y, a, b, U, eps, q):
+        self.X, self.Y, self.a, self.b, self.U = X, Y, a, b, U
+        self.eps, self.q = float(eps), float(q)
+        self.n, self.d = X.shape
+        self.m = Y.shape[0]
+        self.r = U.shape[0]
+        self.layout = state_layout(self.n, self.m, self.r)
+        self.buf = torch.empty(self.layout.total, dtype=torch.uint8,
+                               device=X.device)
+        self.problem = sk_problem(X.data_ptr(), Y.data_ptr(), a.data_ptr(),
+                                  b.data_ptr(), U.data_ptr(), self.n, self.m,
+                                  self.d, self.r, self.eps, self.q)
+
+    def _view(self, off, count, dtype=torch.float32):
+        nbytes = count * torch.tensor([], dtype=dtype).element_size()
+        return self.buf[off:off + nbytes].view(dtype)
+
+    @property
+    def phix(self):
+        return self._view(self.layout.phix, self.n * self.r).view(self.n, self.r)
+
+    @property
+    def phiy(self):
+        return self._view(self.layout.phiy, self.m * self.r).view(self.m, self.r)
+
+    @property
+    def sx(self):
+        return self._view(self.layout.sx, self.n)
+
+    @property
+    def sy(self):
+        return self._view(self.layout.sy, self.m)
+
+    def scalings(self, k):
+        """(u, v, w, z) of solve k: 0 = (x,y), 1 = (x,x), 2 = (y,y)."""
+        rows = (self.n, self.n, self.m)[k]
+        cols = (self.m, self.n, self.m)[k]
+        L = self.layout
+        return (self._view(L.u[k], rows), self._view(L.v[k], cols),
+                self._view(L.w[k], self.r), self._view(L.z[k], self.r))
+
+    def infos(self) -> np.ndarray:
+        return parse_infos(self.buf[self.layout.info:self.layout.info +
+                                    3 * INFO_BYTES])
+
+    @property
+    def out(self):
+        return self._view(self.layout.out, 4, torch.float64)
+
+
+def _check_problem_tensors(X, Y, a, b, U):
+    _need(X, "X")
+    _need(Y, "Y")
+    _need(U, "U")
+    n, d = X.shape
+    m = Y.shape[0]
+    if Y.shape[1] != d or U.shape[1] != d:
+        raise ValueError("X, Y and U need the same dimension d")
+    _need(a, "a", shape=(n,))
+    _need(b, "b", shape=(m,))
+
+
+def divergence_workspace_bytes(state: DivergenceState) -> int:
+    return int(lib().sinkhorn_divergence_workspace_size(ctypes.byref(state.problem)))
+
+
+def divergence(X, Y, a, b, U, eps, q, tol=1e-6, max_iter=2000, fixed_iter=0,
+               workspace: Optional[torch.Tensor] = None,
+               state: Optional[DivergenceState] = None):
+    """Debiased divergence.  Returns (out, state) with out a device float64
+    tensor [W_bar, W_xy, W_xx, W_yy] (asynchronous)."""
+    _check_problem_tensors(X, Y, a, b, U)
+    if state is None:
+        state = DivergenceState(X, Y, a, b, U, eps, q)
+    need = divergence_workspace_bytes(state)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=X.device)
+    out = torch.empty(4, dtype=torch.float64, device=X.device)
+    o = _opts(tol, max_iter, fixed_iter)
+    check(lib().sinkhorn_divergence(ctypes.byref(state.problem), ctypes.byref(o),
+                                    _ptr(out), _ptr(state.buf),
+                                    state.buf.numel(), _ptr(workspace),
+                                    workspace.numel(), _stream(X.device)),
+          "sinkhorn_divergence")
+    state.workspace = workspace
+    return out, state
+
+
+def divergence_backward(state: DivergenceState,
+                        grad_out: Optional[torch.Tensor] = None,
+                        need=(True, True, True, True)):
+    """Gradients (dX, da, dY, db) of the divergence held in `state`."""
+    dev = state.X.device
+    dX = torch.empty_like(state.X) if need[0] else None
+    da = torch.empty_like(state.a) if need[1] else None
+    dY = torch.empty_like(state.Y) if need[2] else None
+    db = torch.empty_like(state.b) if need[3] else None
+    ws = getattr(state, "workspace", None)
+    if ws is None or ws.numel() < 32768:
+        ws = torch.empty(32768, dtype=torch.uint8, device=dev)
+    if grad_out is not None:
+        grad_out = grad_out.detach().to(device=dev, dtype=torch.float32).reshape(1).contiguous()
+    check(lib().sinkhorn_divergence_backward(
+        ctypes.byref(state.problem), _ptr(state.buf), _ptr(grad_out), _ptr(dX),
+        _ptr(da), _ptr(dY), _ptr(db), _ptr(ws), ws.numel(), _stream(dev)),
+        "sinkhorn_divergence_backward")
+    return dX, da, dY, db
+
+
+def features_backward(X, U, Phi, p, g, coef=1.0, dX=None, accumulate=False):
+    """dX (+)= coef * 4 p_i (x_i (Phi_i . g) - sum_k Phi_ik g_k u_k)."""
+    n, d = X.shape
+    r = U.shape[0]
+    if dX is None:
+        dX = torch.zeros_like(X)
+    check(lib().sinkhorn_features_backward(_ptr(X), n, d, _ptr(U), r, _ptr(Phi),
+                                           _ptr(p), _ptr(g), float(coef),
+                                           int(accumulate), _ptr(dX),
+                                           _stream(X.device)),
+          "sinkhorn_features_backward")
+    return dX
+
+
+# ------------------------------------------------------------------ (a6)
+def divergence_batched(problems: Sequence[tuple], tol=1e-6, max_iter=2000,
+                       fixed_iter=0, workspace: Optional[torch.Tensor] = None):
+    """Many divergences in batched launches.  ``problems`` holds tuples
+    (X, Y, a, b, U, eps, q).  Returns (out (count, 4) float64, states)."""
+    states: List[DivergenceState] = []
+    for P in problems:
+        _check_problem_tensors(*P[:5])
+        states.append(DivergenceState(*P))
+    count = len(states)
+    dev = states[0].X.device
+    arr = (sk_problem * count)(*[s.problem for s in states])
+    need = int(lib().sinkhorn_batched_workspace_size(arr, count))
+    if need == 0:
+        raise ValueError("invalid batch")
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    out = torch.empty((count, 4), dtype=torch.float64, device=dev)
+    ptrs = (ctypes.c_void_p * count)(*[s.buf.data_ptr() for s in states])
+    o = _opts(tol, max_iter, fixed_iter)
+    check(lib().sinkhorn_divergence_batched(arr, count, ctypes.byref(o),
+                                            _ptr(out), ptrs, _ptr(workspace),
+                                            workspace.numel(), _stream(dev)),
+          "sinkhorn_divergence_batched")
+    for s in states:
+        s.workspace = workspace
+    return out, states
+
+
+# ------------------------------------------------------------------ (a8)
+class _SinkhornDivergenceFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, X, Y, a, b, U, eps, q, tol, max_iter, fixed_iter):
+        out, state = divergence(X, Y, a, b, U, eps, q, tol, max_iter, fixed_iter)
+        ctx.state = state
+        return out[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        need = (ctx.needs_input_grad[0], ctx.needs_input_grad[2],
+                ctx.needs_input_grad[1], ctx.needs_input_grad[3])
+        dX, da, dY, db = divergence_backward(ctx.state, g, need)
+        return dX, dY, da, db, None, None, None, None, None, None
+
+
+def sinkhorn_divergence(X, Y, a, b, U, eps, q, tol=1e-6, max_iter=2000,
+                        fixed_iter=0):
+    """Differentiable debiased Sinkhorn divergence (float64 scalar tensor);
+    gradients flow to X, Y, a and b through the library's adjoint kernels."""
+    return _SinkhornDivergenceFn.apply(X, Y, a, b, U, eps, q, tol, max_iter,
+                                       fixed_iter)

@@ -1,0 +1,264 @@
+// Adjoint of the divergence with respect to point locations and weights.
+//
+// Prop. 3.2 gives dW/dK = -eps u v^T at the optimum of Eq. (eval-dual); the
+// point-location gradient of Sec. 3.3 pushes it through the feature map.
+// With phi_k(x) = exp(E_k(x)), dE_k/dx = -(4/eps)(x - u_k), and the row
+// scaling absorbed (u_i phi_k(x_i) = u~_i Phi~_ik, Phi_y^T v = Phi~_y^T v~),
+// one side of one solve contributes
+//   T_i(p, g) = 4 p_i ( x_i (Phi~_i . g) - sum_k Phi~_ik g_k u_k ),
+// where (p, g) = (u~, Phi~_y^T v~) on the row side and (v~, Phi~_x^T u~) on
+// the column side.  The kernel evaluates up to three such terms with
+// coefficients in one read of each feature row:
+//   h_ik = sum_t c_t p^t_i g^t_k,  D_i = Phi~_i . h_i,  V_i = sum_k Phi~_ik h_ik u_k,
+//   dX_i (+)= grad_out * 4 (x_i D_i - V_i).
+//
+// Weight gradient (envelope theorem on Eq. eval-dual): dW/da = eps log u on
+// the row side; the dual optimum is unique up to a constant (App. B), so the
+// result is centred.  For the divergence,
+//   da = eps (log u~_xy - (log u~_xx + log v~_xx)/2) - mean.
+#include "sk_internal.h"
+
+#include <math.h>
+
+namespace sk {
+namespace {
+
+constexpr int kAdjLdsFloats = 12288;
+constexpr int kDChunk = 8;  // coordinates reduced per round
+
+template <int G>
+__device__ __forceinline__ float gsum(float x) {
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+__device__ __forceinline__ float4 f4z() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+
+template <int G, int C>
+__global__ void __launch_bounds__(kBlock)
+features_backward_kernel(const float* __restrict__ X, int64_t n, int d,
+                         const float* __restrict__ U, int r,
+                         const float* __restrict__ Phi,
+                         const float* __restrict__ p1, const float* __restrict__ g1, float c1,
+                         const float* __restrict__ p2, const float* __restrict__ g2, float c2,
+                         const float* __restrict__ p3, const float* __restrict__ g3, float c3,
+                         const float* __restrict__ grad_out, int accumulate,
+                         float* __restrict__ dX) {
+  __shared__ float Ut[kAdjLdsFloats];
+  constexpr int RPW = 64 / G;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int sub = lane / G;
+  const int cl = lane % G;
+  const int rp = (r + 3) & ~3;
+  const bool in_lds = (int64_t)d * rp <= kAdjLdsFloats;
+  if (in_lds) {
+    for (int idx = threadIdx.x; idx < d * rp; idx += kBlock) {
+      const int dim = idx / rp, k = idx - dim * rp;
+      Ut[idx] = k < r ? U[(int64_t)k * d + dim] : 0.f;
+    }
+  }
+  __syncthreads();
+  float4 G1[C], G2[C], G3[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int col = 4 * cl + 4 * G * c;
+    const bool cv = col < r;
+    G1[c] = (cv && g1) ? *reinterpret_cast<const float4*>(g1 + col) : f4z();
+    G2[c] = (cv && g2) ? *reinterpret_cast<const float4*>(g2 + col) : f4z();
+    G3[c] = (cv && g3) ? *reinterpret_cast<const float4*>(g3 + col) : f4z();
+  }
+  const float go = 4.0f * (grad_out ? *grad_out : 1.0f);
+  const int64_t rows_per_block_step = (int64_t)kWaves * RPW;
+  for (int64_t base = (int64_t)blockIdx.x * rows_per_block_step; base < n;
+       base += (int64_t)gridDim.x * rows_per_block_step) {
+    const int64_t row = base + wave * RPW + sub;
+    const bool rv = row < n;
+    const float q1 = (rv && p1) ? c1 * p1[row] : 0.f;
+    const float q2 = (rv && p2) ? c2 * p2[row] : 0.f;
+    const float q3 = (rv && p3) ? c3 * p3[row] : 0.f;
+    float4 ph[C];
+    float Dl = 0.f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int col = 4 * cl + 4 * G * c;
+      float4 x = (rv && col < r)
+                     ? *reinterpret_cast<const float4*>(Phi + row * (int64_t)r + col)
+                     : f4z();
+      float4 h;
+      h.x = q1 * G1[c].x + q2 * G2[c].x + q3 * G3[c].x;
+      h.y = q1 * G1[c].y + q2 * G2[c].y + q3 * G3[c].y;
+      h.z = q1 * G1[c].z + q2 * G2[c].z + q3 * G3[c].z;
+      h.w = q1 * G1[c].w + q2 * G2[c].w + q3 * G3[c].w;
+      ph[c] = make_float4(x.x * h.x, x.y * h.y, x.z * h.z, x.w * h.w);
+      Dl += (ph[c].x + ph[c].y) + (ph[c].z + ph[c].w);
+    }
+    const float D = gsum<G>(Dl);
+    for (int d0 = 0; d0 < d; d0 += kDChunk) {
+      float V[kDChunk];
+#pragma unroll
+      for (int j = 0; j < kDChunk; ++j) V[j] = 0.f;
+#pragma unroll
+      for (int j = 0; j < kDChunk; ++j) {
+        const int dim = d0 + j;
+        if (dim < d) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const int col = 4 * cl + 4 * G * c;
+            if (col < r) {
+              float4 u4;
+              if (in_lds) {
+                u4 = *reinterpret_cast<const float4*>(&Ut[dim * rp + col]);
+              } else {
+                u4.x = U[(int64_t)(col + 0) * d + dim];
+                u4.y = U[(int64_t)(col + 1) * d + dim];
+                u4.z = U[(int64_t)(col + 2) * d + dim];
+                u4.w = U[(int64_t)(col + 3) * d + dim];
+              }
+              V[j] = fmaf(ph[c].x, u4.x, V[j]);
+              V[j] = fmaf(ph[c].y, u4.y, V[j]);
+              V[j] = fmaf(ph[c].z, u4.z, V[j]);
+              V[j] = fmaf(ph[c].w, u4.w, V[j]);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kDChunk; ++j) V[j] = gsum<G>(V[j]);
+      if (rv && cl == 0) {
+#pragma unroll
+        for (int j = 0; j < kDChunk; ++j) {
+          const int dim = d0 + j;
+          if (dim < d) {
+            const float xk = X[row * (int64_t)d + dim];
+            const float val = go * (xk * D - V[j]);
+            float* o = dX + row * (int64_t)d + dim;
+            *o = accumulate ? *o + val : val;
+          }
+        }
+      }
+    }
+  }
+}
+
+typedef void (*AdjLaunch)(dim3, hipStream_t, const float*, int64_t, int,
+                          const float*, int, const float*, const float*,
+                          const float*, float, const float*, const float*,
+                          float, const float*, const float*, float,
+                          const float*, int, float*);
+
+template <int G, int C>
+void launch_adj(dim3 grid, hipStream_t s, const float* X, int64_t n, int d,
+                const float* U, int r, const float* Phi, const float* p1,
+                const float* g1, float c1, const float* p2, const float* g2,
+                float c2, const float* p3, const float* g3, float c3,
+                const float* go, int acc, float* dX) {
+  hipLaunchKernelGGL((features_backward_kernel<G, C>), grid, dim3(kBlock), 0, s,
+                     X, n, d, U, r, Phi, p1, g1, c1, p2, g2, c2, p3, g3, c3, go,
+                     acc, dX);
+}
+
+struct AdjClass {
+  int rmax;
+  int rpw;
+  AdjLaunch launch;
+};
+
+#define SK_ACLASS(G, C) { 4 * (G) * (C), 64 / (G), &launch_adj<G, C> }
+
+const AdjClass kAdj[] = {
+    SK_ACLASS(1, 1),   SK_ACLASS(2, 1),   SK_ACLASS(4, 1),  SK_ACLASS(8, 1),
+    SK_ACLASS(16, 1),  SK_ACLASS(32, 1),  SK_ACLASS(64, 1), SK_ACLASS(64, 2),
+    SK_ACLASS(64, 3),  SK_ACLASS(64, 4),  SK_ACLASS(64, 6), SK_ACLASS(64, 8),
+    SK_ACLASS(64, 12), SK_ACLASS(64, 16),
+};
+
+// ------------------------------------------------------------ weight grad
+__global__ void __launch_bounds__(kBlock)
+weight_grad_partial(const float* __restrict__ u1, const float* __restrict__ u2,
+                    const float* __restrict__ u3, int64_t n, double eps,
+                    double* __restrict__ part) {
+  __shared__ double sh[kBlock];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    s += eps * (log((double)u1[i]) -
+                0.5 * (log((double)u2[i]) + log((double)u3[i])));
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(kBlock)
+weight_grad_final(const float* __restrict__ u1, const float* __restrict__ u2,
+                  const float* __restrict__ u3, int64_t n, double eps,
+                  const double* __restrict__ part, int nparts,
+                  const float* __restrict__ grad_out, float* __restrict__ da) {
+  __shared__ double sh[kBlock];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double mean = sh[0] / (double)n;
+  const double go = grad_out ? (double)*grad_out : 1.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    const double raw = eps * (log((double)u1[i]) -
+                              0.5 * (log((double)u2[i]) + log((double)u3[i])));
+    da[i] = (float)(go * (raw - mean));
+  }
+}
+
+}  // namespace
+
+hipError_t launch_features_backward(const float* X, int64_t n, int d,
+                                    const float* U, int r, const float* Phi,
+                                    const float* p1, const float* g1, float c1,
+                                    const float* p2, const float* g2, float c2,
+                                    const float* p3, const float* g3, float c3,
+                                    const float* grad_out, int accumulate,
+                                    float* dX, hipStream_t s) {
+  if (r % 4 != 0) return hipErrorInvalidValue;
+  const AdjClass* cls = nullptr;
+  for (const AdjClass& c : kAdj)
+    if (r <= c.rmax) { cls = &c; break; }
+  if (!cls) return hipErrorInvalidValue;
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t rows_per_block = (int64_t)kWaves * cls->rpw;
+  int64_t grid = (n + rows_per_block - 1) / rows_per_block;
+  if (grid > (int64_t)cus * 16) grid = (int64_t)cus * 16;
+  if (grid < 1) grid = 1;
+  cls->launch(dim3((unsigned)grid), s, X, n, d, U, r, Phi, p1, g1, c1, p2, g2,
+              c2, p3, g3, c3, grad_out, accumulate, dX);
+  return hipGetLastError();
+}
+
+hipError_t launch_weight_grad(const float* u1, const float* u2,
+                              const float* u3, int64_t n, double eps,
+                              const float* grad_out, double* scratch,
+                              int scratch_blocks, float* da, hipStream_t s) {
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > scratch_blocks) blocks = scratch_blocks;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(weight_grad_partial, dim3((unsigned)blocks), dim3(kBlock),
+                     0, s, u1, u2, u3, n, eps, scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(weight_grad_final, dim3((unsigned)blocks), dim3(kBlock), 0,
+                     s, u1, u2, u3, n, eps, scratch, (int)blocks, grad_out, da);
+  return hipGetLastError();
+}
+
+}  // namespace sk

@@ -1,0 +1,280 @@
+// Row-scaled positive Gaussian features (Lemma 1, Sec. 3.2; Eq. general).
+//
+// For point x_i and anchor u_k the log-feature is
+//   E_ik = -log(r)/2 + (d/4) log(2q) - (2/eps)||x_i - u_k||^2 + ||u_k||^2/(eps q)
+// and the kernel writes s_i = max_k E_ik and Phi_ik = exp(E_ik - s_i).
+//
+// This is the direct-difference path: squared distances are summed over the
+// d coordinates in float32 (no ||x||^2 + ||u||^2 - 2 x.u expansion, so no
+// cancellation).  Anchors are staged transposed (d x r) in LDS once per
+// workgroup and problem; each lane owns fixed columns of the output rows,
+// keeps their E values in registers, and the row maximum is a butterfly
+// max over the lanes of the row.  The kernel is write-bound for small d:
+// it writes 4r bytes per point and reads 4d.
+#include "sk_internal.h"
+
+#include <math.h>
+
+namespace sk {
+namespace {
+
+constexpr int kFeatLdsFloats = 12288;  // 48 KB of transposed anchors
+constexpr int kRowsPerWaveTile = 4;
+
+template <int G>
+__device__ __forceinline__ float group_max(float x) {
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+template <int G, int C, int VEC>
+__global__ void __launch_bounds__(kBlock)
+features_kernel(const FeatDesc* __restrict__ descs, int count, FeatDesc one,
+                int64_t total_tiles) {
+  __shared__ float Ut[kFeatLdsFloats];
+  constexpr int RPW = 64 / G;
+  constexpr int TR = kWaves * RPW * kRowsPerWaveTile;  // rows per tile
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int sub = lane / G;
+  const int cl = lane % G;
+
+  const int64_t t0 = total_tiles * blockIdx.x / gridDim.x;
+  const int64_t t1 = total_tiles * (blockIdx.x + 1) / gridDim.x;
+
+  int cur = -1;
+  FeatDesc D{};
+  bool in_lds = false;
+  int rp = 0;
+  float cval[C][VEC];
+  float neg2e = 0.f;
+
+  for (int64_t t = t0; t < t1; ++t) {
+    int lo = 0, hi = count - 1;
+    if (descs) {
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+      }
+    }
+    if (lo != cur) {
+      __syncthreads();
+      cur = lo;
+      D = descs ? descs[lo] : one;
+      const int r = D.r, d = D.d;
+      rp = (r + 3) & ~3;
+      in_lds = (int64_t)d * rp <= kFeatLdsFloats;
+      if (in_lds) {
+        for (int idx = threadIdx.x; idx < d * rp; idx += kBlock) {
+          const int dim = idx / rp, k = idx - dim * rp;
+          Ut[idx] = k < r ? D.U[(int64_t)k * d + dim] : 0.f;
+        }
+      }
+      __syncthreads();
+      const float eps = D.eps, q = D.q;
+      neg2e = -2.0f / eps;
+      const float cst = -0.5f * logf((float)r) + 0.25f * (float)d * logf(2.0f * q);
+      const float inv_eq = 1.0f / (eps * q);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const int col = VEC * cl + VEC * G * c + v;
+          float un = 0.f;
+          if (col < r) {
+            for (int dim = 0; dim < d; ++dim) {
+              const float uk = in_lds ? Ut[dim * rp + col] : D.U[(int64_t)col * d + dim];
+              un = fmaf(uk, uk, un);
+            }
+          }
+          cval[c][v] = fmaf(un, inv_eq, cst);
+        }
+      }
+    }
+    const int r = D.r, d = D.d;
+    const int64_t row0 = (t - D.tile0) * TR;
+#pragma unroll 1
+    for (int rt = 0; rt < kRowsPerWaveTile; ++rt) {
+      const int64_t row = row0 + (int64_t)(rt * kWaves + wave) * RPW + sub;
+      const bool rv = row < D.n;
+      float e[C][VEC];
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) e[c][v] = 0.f;
+      const float* xr = D.X + (rv ? row : 0) * (int64_t)d;
+      for (int dim = 0; dim < d; ++dim) {
+        const float xk = xr[dim];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const int col0 = VEC * cl + VEC * G * c;
+          if constexpr (VEC == 4) {
+            if (in_lds) {
+              // masked columns (col0 >= r) read a valid dummy entry
+              const int cidx = col0 < r ? col0 : 0;
+              const float4 u4 = *reinterpret_cast<const float4*>(&Ut[dim * rp + cidx]);
+              float df;
+              df = xk - u4.x; e[c][0] = fmaf(df, df, e[c][0]);
+              df = xk - u4.y; e[c][1] = fmaf(df, df, e[c][1]);
+              df = xk - u4.z; e[c][2] = fmaf(df, df, e[c][2]);
+              df = xk - u4.w; e[c][3] = fmaf(df, df, e[c][3]);
+              continue;
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) {
+            const int col = col0 + v;
+            const int cc = col < r ? col : 0;
+            const float uk = in_lds ? Ut[dim * rp + cc] : D.U[(int64_t)cc * d + dim];
+            const float df = xk - uk;
+            e[c][v] = fmaf(df, df, e[c][v]);
+          }
+        }
+      }
+      float mx = -INFINITY;
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const int col = VEC * cl + VEC * G * c + v;
+          e[c][v] = col < r ? fmaf(neg2e, e[c][v], cval[c][v]) : -INFINITY;
+          mx = fmaxf(mx, e[c][v]);
+        }
+      mx = group_max<G>(mx);
+      if (rv) {
+        float* orow = D.Phi + row * (int64_t)r;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const int col0 = VEC * cl + VEC * G * c;
+          if constexpr (VEC == 4) {
+            if (col0 < r) {
+              float4 o;
+              o.x = expf(e[c][0] - mx);
+              o.y = expf(e[c][1] - mx);
+              o.z = expf(e[c][2] - mx);
+              o.w = expf(e[c][3] - mx);
+              *reinterpret_cast<float4*>(orow + col0) = o;
+            }
+          } else {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+              const int col = col0 + v;
+              if (col < r) orow[col] = expf(e[c][v] - mx);
+            }
+          }
+        }
+        if (cl == 0) D.s[row] = mx;
+      }
+    }
+  }
+}
+
+typedef void (*FeatLaunch)(dim3, hipStream_t, const FeatDesc*, int,
+                           const FeatDesc&, int64_t);
+
+template <int G, int C, int VEC>
+void launch_feat(dim3 grid, hipStream_t s, const FeatDesc* d, int count,
+                 const FeatDesc& one, int64_t tiles) {
+  hipLaunchKernelGGL((features_kernel<G, C, VEC>), grid, dim3(kBlock), 0, s, d,
+                     count, one, tiles);
+}
+
+struct FeatClass {
+  int rmax;
+  int vec;
+  int rows_per_tile;
+  FeatLaunch launch;
+};
+
+#define SK_FCLASS(G, C, VEC) \
+  { (VEC) * (G) * (C), VEC, kWaves * (64 / (G)) * kRowsPerWaveTile, &launch_feat<G, C, VEC> }
+
+const FeatClass kFeat4[] = {
+    SK_FCLASS(1, 1, 4),   SK_FCLASS(2, 1, 4),   SK_FCLASS(4, 1, 4),
+    SK_FCLASS(8, 1, 4),   SK_FCLASS(16, 1, 4),  SK_FCLASS(32, 1, 4),
+    SK_FCLASS(64, 1, 4),  SK_FCLASS(64, 2, 4),  SK_FCLASS(64, 3, 4),
+    SK_FCLASS(64, 4, 4),  SK_FCLASS(64, 6, 4),  SK_FCLASS(64, 8, 4),
+    SK_FCLASS(64, 12, 4), SK_FCLASS(64, 16, 4),
+};
+const FeatClass kFeat1[] = {
+    SK_FCLASS(64, 1, 1),  SK_FCLASS(64, 2, 1),  SK_FCLASS(64, 4, 1),
+    SK_FCLASS(64, 8, 1),  SK_FCLASS(64, 16, 1), SK_FCLASS(64, 32, 1),
+    SK_FCLASS(64, 64, 1),
+};
+
+const FeatClass* feat_class(int r) {
+  if (r % 4 == 0) {
+    for (const FeatClass& c : kFeat4)
+      if (r <= c.rmax) return &c;
+  } else {
+    for (const FeatClass& c : kFeat1)
+      if (r <= c.rmax) return &c;
+  }
+  return nullptr;
+}
+
+int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+            hipSuccess || cus <= 0)
+      cus = 256;
+  }
+  return cus;
+}
+
+int64_t feature_grid(int64_t tiles) {
+  int64_t grid = (int64_t)device_cus() * 8;
+  if (grid > tiles) grid = tiles;
+  if (grid < 1) grid = 1;
+  return grid;
+}
+
+}  // namespace
+
+hipError_t launch_features(const float* X, int64_t n, int d, const float* U,
+                           int r, double eps, double q, float* Phi,
+                           float* logscale, hipStream_t s) {
+  const FeatClass* cls = feat_class(r);
+  if (!cls) return hipErrorInvalidValue;
+  FeatDesc one{};
+  one.X = X; one.U = U; one.Phi = Phi; one.s = logscale;
+  one.n = n; one.d = d; one.r = r;
+  one.eps = (float)eps; one.q = (float)q; one.tile0 = 0;
+  const int64_t tiles = (n + cls->rows_per_tile - 1) / cls->rows_per_tile;
+  cls->launch(dim3((unsigned)feature_grid(tiles)), s, nullptr, 1, one, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_features_batched(const FeatDesc* host, int count,
+                                   FeatDesc* dev_scratch, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  // All problems of one call share the feature class; the caller groups.
+  const FeatClass* cls = feat_class(host[0].r);
+  if (!cls) return hipErrorInvalidValue;
+  FeatDesc* tmp = new FeatDesc[count];
+  int64_t tiles = 0;
+  for (int i = 0; i < count; ++i) {
+    tmp[i] = host[i];
+    tmp[i].tile0 = tiles;
+    tiles += (host[i].n + cls->rows_per_tile - 1) / cls->rows_per_tile;
+  }
+  // descriptors go up with stream-ordered kernels (graph capturable)
+  hipError_t e = upload_bytes(dev_scratch, tmp, sizeof(FeatDesc) * (size_t)count, s);
+  const FeatDesc one = tmp[0];
+  delete[] tmp;
+  if (e != hipSuccess) return e;
+  cls->launch(dim3((unsigned)feature_grid(tiles)), s, dev_scratch, count, one,
+              tiles);
+  return hipGetLastError();
+}
+
+int features_class_rmax(int r) {
+  const FeatClass* c = feat_class(r);
+  return c ? c->rmax : 0;
+}
+
+}  // namespace sk

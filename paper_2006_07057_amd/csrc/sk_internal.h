@@ -1,0 +1,128 @@
+// Internal declarations shared by the library's translation units.
+// Not part of the public ABI (that is include/sinkhorn.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/sinkhorn.h"
+
+namespace sk {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+constexpr int kWaves = kBlock / 64;
+
+// One run of Algorithm 1 on K = Prow Pcol^T, as seen by the persistent
+// solver.  Device-resident (uploaded into the workspace).
+struct SolveDesc {
+  const float* Prow;     // n x r, row side (scaling u)
+  const float* Pcol;     // m x r, column side (scaling v)
+  const float* a;        // n
+  const float* b;        // m
+  const float* srow;     // n log-scales of Prow or nullptr
+  const float* scol;     // m log-scales of Pcol or nullptr
+  float* u;              // n: start (warm) / result
+  float* v;              // m: result
+  float* v2;             // m: second buffer of v (stop test needs v^(k-1))
+  float* w;              // r: result Pcol^T v
+  float* w2;             // r: second buffer of w
+  float* z;              // r: result Prow^T u
+  float* slots;          // per-workgroup partial r-vectors, stride slot_stride
+  int32_t* members;      // g entries: workgroup index holding each seat
+  double* dpart;         // 4 x g float64 partials (error, flags, dual sums)
+  unsigned* bar;         // group barrier counter (zeroed before the launch)
+  sk_solve_info* info;   // result record
+  double tol;
+  double eps;
+  int64_t n, m;
+  int32_t r;
+  int32_t g;             // workgroups that run this solve together
+  int32_t max_iter;
+  int32_t fixed_iter;
+  int32_t warm;
+  int32_t seat0;         // first seat index of this solve in the launch
+  int32_t slot_stride;   // floats between consecutive workgroup slots
+  int32_t pad0;
+};
+
+// Launch-wide control block (zeroed by init_ctl before each launch).
+struct LaunchCtl {
+  unsigned next_seat;
+  unsigned abort_flag;
+  unsigned pad[62];
+};
+
+// Largest group size (workgroups per solve) the library plans with; it
+// bounds workspace sizes independently of the device.
+constexpr int kMaxGroup = 2048;
+
+// Largest r of the solver class that handles feature count r (0 if none).
+int solver_class_rmax(int r);
+
+// Maximum number of co-resident workgroups of the solver for feature
+// count r on the current device (0 on error).
+int solver_capacity(int r);
+
+// Group size the scheduler gives a solve with these sizes.
+int solver_group_size(int64_t n, int64_t m, int r, int capacity);
+
+// Copy host bytes to device memory with stream-ordered kernel launches
+// (the bytes travel as kernel arguments), so the copy can be graph-captured
+// and the host buffer may be reused as soon as the call returns.
+hipError_t upload_bytes(void* dev, const void* host, size_t nbytes,
+                        hipStream_t s);
+
+// Upload `count` solve descriptors (host array) to dev (device array) with
+// stream-ordered kernel launches, so the upload can be graph-captured.
+hipError_t upload_descs(SolveDesc* dev, const SolveDesc* host, int count,
+                        hipStream_t s);
+
+// Run all solves in `dev_descs` (count entries, all with the same r class)
+// in one persistent launch.  total_seats = sum of g.
+hipError_t launch_solver(const SolveDesc* dev_descs, int count, int r,
+                         int total_seats, int grid, LaunchCtl* ctl,
+                         hipStream_t s);
+
+// Features (row-scaled Gaussian positive features).
+hipError_t launch_features(const float* X, int64_t n, int d, const float* U,
+                           int r, double eps, double q, float* Phi,
+                           float* logscale, hipStream_t s);
+
+// Batched features over several (X, U) problems.
+struct FeatDesc {
+  const float* X;
+  const float* U;
+  float* Phi;
+  float* s;
+  int64_t n;
+  int32_t d, r;
+  float eps, q;
+  int64_t tile0;         // first row-tile index of this problem
+};
+hipError_t launch_features_batched(const FeatDesc* host, int count,
+                                   FeatDesc* dev_scratch, hipStream_t s);
+
+// Divergence assembly: out[4*i..] from infos of solves (3 per problem).
+hipError_t launch_assemble(const sk_solve_info* const* infos_xy_xx_yy,
+                           double* const* outs, int count, hipStream_t s);
+
+// Adjoint kernels.
+hipError_t launch_features_backward(const float* X, int64_t n, int d,
+                                    const float* U, int r, const float* Phi,
+                                    const float* p1, const float* g1, float c1,
+                                    const float* p2, const float* g2, float c2,
+                                    const float* p3, const float* g3, float c3,
+                                    const float* grad_out, int accumulate,
+                                    float* dX, hipStream_t s);
+hipError_t launch_weight_grad(const float* u1, const float* u2,
+                              const float* u3, int64_t n, double eps,
+                              const float* grad_out, double* scratch,
+                              int scratch_blocks, float* da, hipStream_t s);
+
+hipError_t launch_init_ctl(LaunchCtl* ctl, unsigned* bars, int nbars,
+                           hipStream_t s);
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace sk
