@@ -66,6 +66,19 @@ enum {
 /* Largest number of features per point supported by the solver. */
 #define SK_MAX_R 4096
 
+/* Numeric domain of the scaling loop (sk_solve_opts.range).
+ *   SK_RANGE_EXTENDED (default): features are stored as log2 values
+ *     L = log2(Phi) and every scaling / r-vector entry as a pair
+ *     (E, M) meaning M * 2^E (E integer-valued, M a float32 mantissa),
+ *     stored as two halves [E(len) | M(len)].  Relative precision is that
+ *     of float32 arithmetic; the range covers scalings far beyond float32
+ *     (well-separated clouds, small eps).
+ *   SK_RANGE_LINEAR: plain float32 features, scalings and r-vectors.
+ *     Faster, but fails with SK_ERANGE when the scalings leave the float32
+ *     range. */
+#define SK_RANGE_EXTENDED 0
+#define SK_RANGE_LINEAR 1
+
 /* Options of Algorithm 1 (Sec. 2).
  *   tol        stop after the first iteration whose column marginal error
  *              ||v o K^T u - b||_1 (computed in float64) is below tol;
@@ -75,13 +88,14 @@ enum {
  *              (the final error is still measured and reported);
  *   warm_start if nonzero, the u buffer passed to sinkhorn_solve holds the
  *              starting (positive) scaling; otherwise u starts at 1.  Any
- *              positive start is allowed by Sec. 2. */
+ *              positive start is allowed by Sec. 2;
+ *   range      numeric domain, see SK_RANGE_EXTENDED / SK_RANGE_LINEAR. */
 typedef struct {
   double tol;
   int32_t max_iter;
   int32_t fixed_iter;
   int32_t warm_start;
-  int32_t reserved;
+  int32_t range;      /* SK_RANGE_EXTENDED (0) or SK_RANGE_LINEAR (1) */
 } sk_solve_opts;
 
 /* Outcome of one run of Algorithm 1, written by the device.
@@ -112,17 +126,18 @@ int sinkhorn_gaussian_q(double R, double eps, int64_t d, double* q_host);
  *   E_ik = -log(r)/2 + (d/4) log(2q) - (2/eps)||x_i - u_k||^2
  *          + ||u_k||^2 / (eps q),
  * so phi_theta(x_i)_k = exp(E_ik).  The call writes
- *   logscale[i] = s_i = max_k E_ik            (n floats)
- *   Phi[i*r+k]  = exp(E_ik - s_i) in (0, 1]   (n x r floats)
- * i.e. Phi_theta = diag(exp(s)) Phi.  The factor exp(s) is absorbed exactly
- * by the Sinkhorn scalings (u = u~ exp(-s)), which keeps every feature
- * representable in float32.
+ *   logscale[i] = s_i = max_k E_ik                   (n floats)
+ *   Phi[i*r+k]  = exp(E_ik - s_i) in (0, 1]          (SK_RANGE_LINEAR)
+ *              or (E_ik - s_i) log2(e) <= 0          (SK_RANGE_EXTENDED)
+ * i.e. Phi_theta = diag(exp(s)) Phi (Phi = 2^L in the extended range).  The
+ * factor exp(s) is absorbed exactly by the Sinkhorn scalings
+ * (u = u~ exp(-s)).
  * Arguments: X (n x d), U (r x d) device float32; eps > 0; q > 1/2;
  * 1 <= r <= SK_MAX_R, d >= 1, n >= 1.  Phi and logscale must not overlap X
  * or U.  Errors: SK_EINVAL for bad sizes/pointers/eps/q. */
 int sinkhorn_features(const float* X, int64_t n, int64_t d, const float* U,
-                      int64_t r, double eps, double q, float* Phi,
-                      float* logscale, sk_stream_t stream);
+                      int64_t r, double eps, double q, int32_t range,
+                      float* Phi, float* logscale, sk_stream_t stream);
 
 /* ------------------------------------------------------------- (a3)(a4) */
 /* Workspace bytes needed by sinkhorn_solve for these sizes (host). */
@@ -132,10 +147,13 @@ size_t sinkhorn_solve_workspace_size(int64_t n, int64_t m, int64_t r);
  * iteration v <- b / (Phiy (Phix^T u)), u <- a / (Phix (Phiy^T v)) done as
  * two fused passes that read each feature row once, until the float64 L1
  * column-marginal error drops below opts->tol (or per opts->fixed_iter).
- * Inputs:  Phix (n x r), Phiy (m x r) positive features; a (n), b (m)
- *          positive weights.  r % 4 == 0, r <= SK_MAX_R.
+ * Inputs:  Phix (n x r), Phiy (m x r) positive features (log2 features in
+ *          the extended range); a (n), b (m) positive weights.
+ *          r % 4 == 0, r <= SK_MAX_R.
  * Outputs: u (n), v (m) scalings; w = Phiy^T v (r), z = Phix^T u (r)
- *          (the r-vectors the adjoint needs); *info (device).
+ *          (the r-vectors the adjoint needs); *info (device).  In the
+ *          extended range every one of them is a pair array [E | M] of
+ *          twice the length (2n, 2m, 2r, 2r floats).
  *          u is read as the starting point when opts->warm_start != 0.
  * ws:      device workspace of at least sinkhorn_solve_workspace_size bytes,
  *          used as scratch (contents on entry are ignored).
@@ -166,10 +184,12 @@ typedef struct {
 typedef struct {
   size_t phix, phiy;      /* float n x r, m x r   row-scaled features */
   size_t sx, sy;          /* float n, m           row log-scales */
-  size_t u[3], v[3];      /* float scalings of the (x,y), (x,x), (y,y) solves */
-  size_t w[3], z[3];      /* float r: w = Phi_col^T v, z = Phi_row^T u */
+  size_t u[3], v[3];      /* scalings of the (x,y), (x,x), (y,y) solves */
+  size_t w[3], z[3];      /* r-vectors: w = Phi_col^T v, z = Phi_row^T u */
+                          /* (each sized for the [E | M] pair layout) */
   size_t info;            /* sk_solve_info[3] */
   size_t out;             /* double[4]: W_bar, W_xy, W_xx, W_yy */
+  size_t meta;            /* int32[4]: [0] = numeric domain used */
   size_t total;           /* total bytes */
 } sk_state_layout;
 
@@ -220,12 +240,14 @@ int sinkhorn_divergence_batched(const sk_problem* problems, int32_t count,
  * scaling p (n) and r-vector g (w for the row side, z for the column side):
  *   dX[i] (+)= coef * 4 p_i ( x_i (Phi_i . g) - sum_k Phi_ik g_k u_k )
  * with Phi the row-scaled features of X (so p is the matching scaled
- * scaling).  accumulate != 0 adds to dX, otherwise overwrites it.
- * Errors: SK_EINVAL. */
+ * scaling).  accumulate != 0 adds to dX, otherwise overwrites it.  range
+ * gives the layout of Phi, p and g (as written by sinkhorn_features and
+ * sinkhorn_solve with that range).
+ * Errors: SK_EINVAL, SK_ENOTSUP (r % 4 != 0). */
 int sinkhorn_features_backward(const float* X, int64_t n, int64_t d,
                                const float* U, int64_t r, const float* Phi,
                                const float* p, const float* g, float coef,
-                               int32_t accumulate, float* dX,
+                               int32_t accumulate, int32_t range, float* dX,
                                sk_stream_t stream);
 
 /* Gradient of the divergence computed by sinkhorn_divergence (same problem
@@ -234,12 +256,27 @@ int sinkhorn_features_backward(const float* X, int64_t n, int64_t d,
  *   dX = G_row(xy) - (G_row(xx) + G_col(xx)) / 2,   G from the call above;
  *   da = eps (log u_xy - (log u_xx + log v_xx) / 2), centred (mean removed:
  *        the dual optimum is unique only up to a constant, App. B);
- * and symmetrically for dY, db.  Any of dX, da, dY, db may be NULL.
+ * and symmetrically for dY, db.  Any of dX, da, dY, db may be NULL.  The
+ * numeric domain is the one recorded in the state by the forward call.
  * ws: sinkhorn_divergence_workspace_size bytes.  Errors: SK_EINVAL. */
 int sinkhorn_divergence_backward(const sk_problem* p, const void* state,
                                  const float* grad_out, float* dX, float* da,
                                  float* dY, float* db, void* ws,
                                  size_t ws_bytes, sk_stream_t stream);
+
+/* ------------------------------------------------------- instrumentation */
+/* Launch timing for measurement: with enable != 0, every later launch of
+ * the solver (kind 0), feature (kind 1) and adjoint (kind 2) kernels is
+ * bracketed by two HIP events recorded on the launch's own stream.  Calling
+ * it again clears the records.  Not for use under graph capture.
+ * Returns SK_OK. */
+int sinkhorn_profile(int32_t enable);
+
+/* Sum (*total_ms), count (*launches) and maximum (*max_ms, may be NULL) of
+ * the recorded launch durations of one kind; waits for the recorded events.
+ * Errors: SK_EINVAL (NULL outputs), SK_EHIP. */
+int sinkhorn_profile_read(int32_t kind, double* total_ms, int64_t* launches,
+                          double* max_ms);
 
 /* Human-readable name of a status code (static string). */
 const char* sinkhorn_strerror(int status);

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libsinkhorn.so")
 SK_OK, SK_EINVAL, SK_ENOMEM, SK_ERANGE, SK_ENOTCONV, SK_EHIP, SK_ETIMEOUT, \
     SK_ENOTSUP = range(8)
 SK_MAX_R = 4096
+SK_RANGE_EXTENDED, SK_RANGE_LINEAR = 0, 1
 
 c_i32, c_i64, c_f32p, c_dbl = ctypes.c_int32, ctypes.c_int64, \
     ctypes.c_void_p, ctypes.c_double
@@ -23,7 +24,7 @@ c_size, c_void = ctypes.c_size_t, ctypes.c_void_p
 class sk_solve_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", c_i32),
                 ("fixed_iter", c_i32), ("warm_start", c_i32),
-                ("reserved", c_i32)]
+                ("range", c_i32)]
 
 
 class sk_solve_info(ctypes.Structure):
@@ -41,7 +42,7 @@ class sk_state_layout(ctypes.Structure):
     _fields_ = [("phix", c_size), ("phiy", c_size), ("sx", c_size),
                 ("sy", c_size), ("u", c_size * 3), ("v", c_size * 3),
                 ("w", c_size * 3), ("z", c_size * 3), ("info", c_size),
-                ("out", c_size), ("total", c_size)]
+                ("out", c_size), ("meta", c_size), ("total", c_size)]
 
 
 # name -> (restype, argtypes)
@@ -49,7 +50,7 @@ SIGNATURES = {
     "sinkhorn_gaussian_q": (c_i32, [c_dbl, c_dbl, c_i64,
                                     ctypes.POINTER(ctypes.c_double)]),
     "sinkhorn_features": (c_i32, [c_void, c_i64, c_i64, c_void, c_i64, c_dbl,
-                                  c_dbl, c_void, c_void, c_void]),
+                                  c_dbl, c_i32, c_void, c_void, c_void]),
     "sinkhorn_solve_workspace_size": (c_size, [c_i64, c_i64, c_i64]),
     "sinkhorn_solve": (c_i32, [c_void, c_i64, c_void, c_i64, c_i64, c_void,
                                c_void, ctypes.POINTER(sk_solve_opts), c_void,
@@ -69,12 +70,16 @@ SIGNATURES = {
                                             c_void, c_size, c_void]),
     "sinkhorn_features_backward": (c_i32, [c_void, c_i64, c_i64, c_void, c_i64,
                                            c_void, c_void, c_void,
-                                           ctypes.c_float, c_i32, c_void,
+                                           ctypes.c_float, c_i32, c_i32, c_void,
                                            c_void]),
     "sinkhorn_divergence_backward": (c_i32, [ctypes.POINTER(sk_problem),
                                              c_void, c_void, c_void, c_void,
                                              c_void, c_void, c_void, c_size,
                                              c_void]),
+    "sinkhorn_profile": (c_i32, [c_i32]),
+    "sinkhorn_profile_read": (c_i32, [c_i32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(c_i64),
+                                      ctypes.POINTER(ctypes.c_double)]),
     "sinkhorn_strerror": (ctypes.c_char_p, [c_i32]),
     "sinkhorn_version": (ctypes.c_char_p, []),
 }

@@ -4,19 +4,28 @@ Every function here only checks and marshals arguments (device pointers,
 sizes, the current HIP stream) and calls the HIP library; all arithmetic of
 the method runs in the library's kernels.  PyTorch provides device memory
 and streams.  Names follow the C ABI (sinkhorn_features, sinkhorn_solve,
-sinkhorn_divergence, ... ) with the ``sinkhorn_`` prefix dropped.
+sinkhorn_divergence, ...) with the ``sinkhorn_`` prefix dropped.
+
+Numeric domain (``range``): EXTENDED (default) stores features as log2
+values and scalings / r-vectors as [exponent | mantissa] halves (twice the
+length); LINEAR stores plain float32 values.  ``host_log_scaling`` decodes
+either layout on the host for inspection.
 """
 from __future__ import annotations
 
 import ctypes
 import dataclasses
+import math
 from typing import List, Optional, Sequence
 
 import numpy as np
 import torch
 
 from . import _lib
-from ._lib import lib, check, sk_problem, sk_solve_opts, sk_state_layout
+from ._lib import (lib, check, sk_problem, sk_solve_opts, sk_state_layout,
+                   SK_RANGE_EXTENDED, SK_RANGE_LINEAR)
+
+EXTENDED, LINEAR = SK_RANGE_EXTENDED, SK_RANGE_LINEAR
 
 INFO_DTYPE = np.dtype([("iters", "<i4"), ("status", "<i4"), ("err", "<f8"),
                        ("w_hat", "<f8")])
@@ -45,14 +54,31 @@ def _need(t: torch.Tensor, name: str, dtype=torch.float32, shape=None):
     return t
 
 
-def _opts(tol=1e-6, max_iter=2000, fixed_iter=0, warm_start=False):
+def _opts(tol=1e-6, max_iter=2000, fixed_iter=0, warm_start=False,
+          range=EXTENDED):
     return sk_solve_opts(float(tol), int(max_iter), int(fixed_iter),
-                         int(bool(warm_start)), 0)
+                         int(bool(warm_start)), int(range))
+
+
+def _width(range):
+    return 2 if range == EXTENDED else 1
 
 
 def parse_infos(raw: torch.Tensor) -> np.ndarray:
     """Decode device sk_solve_info records (synchronises)."""
     return raw.detach().cpu().numpy().view(INFO_DTYPE)
+
+
+def host_log_scaling(t: torch.Tensor, range: int) -> np.ndarray:
+    """Natural log of a scaling or r-vector stored by the library, on the
+    host (float64).  For inspection and tests; synchronises."""
+    a = t.detach().cpu().numpy().astype(np.float64)
+    if range == EXTENDED:
+        k = a.shape[0] // 2
+        with np.errstate(divide="ignore"):
+            return (a[:k] + np.log2(a[k:])) * math.log(2.0)
+    with np.errstate(divide="ignore"):
+        return np.log(a)
 
 
 # ------------------------------------------------------------------ (a1)
@@ -65,9 +91,11 @@ def gaussian_q(R: float, eps: float, d: int) -> float:
 
 
 # ------------------------------------------------------------------ (a2)
-def features(X: torch.Tensor, U: torch.Tensor, eps: float, q: float):
+def features(X: torch.Tensor, U: torch.Tensor, eps: float, q: float,
+             range: int = EXTENDED):
     """Row-scaled Gaussian features: returns (Phi (n, r), s (n,)) with
-    phi_theta(x_i) = exp(s_i) Phi[i]."""
+    phi_theta(x_i) = exp(s_i) Phi[i] (LINEAR) or exp(s_i) 2^Phi[i]
+    (EXTENDED, log2 features)."""
     _need(X, "X")
     _need(U, "U")
     n, d = X.shape
@@ -77,7 +105,7 @@ def features(X: torch.Tensor, U: torch.Tensor, eps: float, q: float):
     Phi = torch.empty((n, r), dtype=torch.float32, device=X.device)
     s = torch.empty((n,), dtype=torch.float32, device=X.device)
     check(lib().sinkhorn_features(_ptr(X), n, d, _ptr(U), r, float(eps),
-                                  float(q), _ptr(Phi), _ptr(s),
+                                  float(q), int(range), _ptr(Phi), _ptr(s),
                                   _stream(X.device)), "sinkhorn_features")
     return Phi, s
 
@@ -90,6 +118,7 @@ class SolveResult:
     w: torch.Tensor
     z: torch.Tensor
     info_raw: torch.Tensor
+    range: int
 
     def info(self):
         return parse_infos(self.info_raw)[0]
@@ -98,8 +127,11 @@ class SolveResult:
 def solve(Phix: torch.Tensor, Phiy: torch.Tensor, a: torch.Tensor,
           b: torch.Tensor, tol: float = 1e-6, max_iter: int = 2000,
           fixed_iter: int = 0, u0: Optional[torch.Tensor] = None,
+          range: int = EXTENDED,
           workspace: Optional[torch.Tensor] = None) -> SolveResult:
-    """Algorithm 1 on K = Phix Phiy^T (asynchronous; read .info() to sync)."""
+    """Algorithm 1 on K = Phix Phiy^T (asynchronous; read .info() to sync).
+    In the EXTENDED range Phix/Phiy are log2 features and u, v, w, z come
+    back as [exponent | mantissa] arrays."""
     _need(Phix, "Phix")
     _need(Phiy, "Phiy")
     n, r = Phix.shape
@@ -109,21 +141,22 @@ def solve(Phix: torch.Tensor, Phiy: torch.Tensor, a: torch.Tensor,
     _need(a, "a", shape=(n,))
     _need(b, "b", shape=(m,))
     dev = Phix.device
-    u = u0.clone() if u0 is not None else torch.empty(n, dtype=torch.float32, device=dev)
-    v = torch.empty(m, dtype=torch.float32, device=dev)
-    w = torch.empty(r, dtype=torch.float32, device=dev)
-    z = torch.empty(r, dtype=torch.float32, device=dev)
+    k = _width(range)
+    u = u0.clone() if u0 is not None else torch.empty(k * n, dtype=torch.float32, device=dev)
+    v = torch.empty(k * m, dtype=torch.float32, device=dev)
+    w = torch.empty(k * r, dtype=torch.float32, device=dev)
+    z = torch.empty(k * r, dtype=torch.float32, device=dev)
     info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=dev)
     need = lib().sinkhorn_solve_workspace_size(n, m, r)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
-    o = _opts(tol, max_iter, fixed_iter, u0 is not None)
+    o = _opts(tol, max_iter, fixed_iter, u0 is not None, range)
     check(lib().sinkhorn_solve(_ptr(Phix), n, _ptr(Phiy), m, r, _ptr(a), _ptr(b),
                                ctypes.byref(o), _ptr(u), _ptr(v), _ptr(w),
                                _ptr(z), _ptr(info), _ptr(workspace),
                                workspace.numel(), _stream(dev)),
           "sinkhorn_solve")
-    return SolveResult(u, v, w, z, info)
+    return SolveResult(u, v, w, z, info, range)
 
 
 # ------------------------------------------------------------------ (a5)
@@ -144,6 +177,7 @@ class DivergenceState:
         self.n, self.d = X.shape
         self.m = Y.shape[0]
         self.r = U.shape[0]
+        self.range = EXTENDED
         self.layout = state_layout(self.n, self.m, self.r)
         self.buf = torch.empty(self.layout.total, dtype=torch.uint8,
                                device=X.device)
@@ -172,12 +206,19 @@ class DivergenceState:
         return self._view(self.layout.sy, self.m)
 
     def scalings(self, k):
-        """(u, v, w, z) of solve k: 0 = (x,y), 1 = (x,x), 2 = (y,y)."""
+        """(u, v, w, z) of solve k: 0 = (x,y), 1 = (x,x), 2 = (y,y), in the
+        layout of the domain used (pairs in the EXTENDED range)."""
         rows = (self.n, self.n, self.m)[k]
         cols = (self.m, self.n, self.m)[k]
         L = self.layout
-        return (self._view(L.u[k], rows), self._view(L.v[k], cols),
-                self._view(L.w[k], self.r), self._view(L.z[k], self.r))
+        c = _width(self.range)
+        return (self._view(L.u[k], c * rows), self._view(L.v[k], c * cols),
+                self._view(L.w[k], c * self.r), self._view(L.z[k], c * self.r))
+
+    def log_scalings(self, k):
+        """Natural logs of (u, v) of solve k on the host (float64)."""
+        u, v, _, _ = self.scalings(k)
+        return host_log_scaling(u, self.range), host_log_scaling(v, self.range)
 
     def infos(self) -> np.ndarray:
         return parse_infos(self.buf[self.layout.info:self.layout.info +
@@ -205,18 +246,19 @@ def divergence_workspace_bytes(state: DivergenceState) -> int:
 
 
 def divergence(X, Y, a, b, U, eps, q, tol=1e-6, max_iter=2000, fixed_iter=0,
-               workspace: Optional[torch.Tensor] = None,
+               range=EXTENDED, workspace: Optional[torch.Tensor] = None,
                state: Optional[DivergenceState] = None):
     """Debiased divergence.  Returns (out, state) with out a device float64
     tensor [W_bar, W_xy, W_xx, W_yy] (asynchronous)."""
     _check_problem_tensors(X, Y, a, b, U)
     if state is None:
         state = DivergenceState(X, Y, a, b, U, eps, q)
+    state.range = int(range)
     need = divergence_workspace_bytes(state)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=X.device)
     out = torch.empty(4, dtype=torch.float64, device=X.device)
-    o = _opts(tol, max_iter, fixed_iter)
+    o = _opts(tol, max_iter, fixed_iter, False, range)
     check(lib().sinkhorn_divergence(ctypes.byref(state.problem), ctypes.byref(o),
                                     _ptr(out), _ptr(state.buf),
                                     state.buf.numel(), _ptr(workspace),
@@ -247,7 +289,8 @@ def divergence_backward(state: DivergenceState,
     return dX, da, dY, db
 
 
-def features_backward(X, U, Phi, p, g, coef=1.0, dX=None, accumulate=False):
+def features_backward(X, U, Phi, p, g, coef=1.0, dX=None, accumulate=False,
+                      range=EXTENDED):
     """dX (+)= coef * 4 p_i (x_i (Phi_i . g) - sum_k Phi_ik g_k u_k)."""
     n, d = X.shape
     r = U.shape[0]
@@ -255,21 +298,24 @@ def features_backward(X, U, Phi, p, g, coef=1.0, dX=None, accumulate=False):
         dX = torch.zeros_like(X)
     check(lib().sinkhorn_features_backward(_ptr(X), n, d, _ptr(U), r, _ptr(Phi),
                                            _ptr(p), _ptr(g), float(coef),
-                                           int(accumulate), _ptr(dX),
-                                           _stream(X.device)),
+                                           int(accumulate), int(range),
+                                           _ptr(dX), _stream(X.device)),
           "sinkhorn_features_backward")
     return dX
 
 
 # ------------------------------------------------------------------ (a6)
 def divergence_batched(problems: Sequence[tuple], tol=1e-6, max_iter=2000,
-                       fixed_iter=0, workspace: Optional[torch.Tensor] = None):
+                       fixed_iter=0, range=EXTENDED,
+                       workspace: Optional[torch.Tensor] = None):
     """Many divergences in batched launches.  ``problems`` holds tuples
     (X, Y, a, b, U, eps, q).  Returns (out (count, 4) float64, states)."""
     states: List[DivergenceState] = []
     for P in problems:
         _check_problem_tensors(*P[:5])
-        states.append(DivergenceState(*P))
+        st = DivergenceState(*P)
+        st.range = int(range)
+        states.append(st)
     count = len(states)
     dev = states[0].X.device
     arr = (sk_problem * count)(*[s.problem for s in states])
@@ -280,7 +326,7 @@ def divergence_batched(problems: Sequence[tuple], tol=1e-6, max_iter=2000,
         workspace = torch.empty(need, dtype=torch.uint8, device=dev)
     out = torch.empty((count, 4), dtype=torch.float64, device=dev)
     ptrs = (ctypes.c_void_p * count)(*[s.buf.data_ptr() for s in states])
-    o = _opts(tol, max_iter, fixed_iter)
+    o = _opts(tol, max_iter, fixed_iter, False, range)
     check(lib().sinkhorn_divergence_batched(arr, count, ctypes.byref(o),
                                             _ptr(out), ptrs, _ptr(workspace),
                                             workspace.numel(), _stream(dev)),
@@ -290,11 +336,31 @@ def divergence_batched(problems: Sequence[tuple], tol=1e-6, max_iter=2000,
     return out, states
 
 
+# ------------------------------------------------------- instrumentation
+PROF_SOLVER, PROF_FEATURES, PROF_ADJOINT = 0, 1, 2
+
+
+def profile(enable: bool = True):
+    """Start (and clear) or stop per-launch event timing in the library."""
+    check(lib().sinkhorn_profile(int(bool(enable))), "sinkhorn_profile")
+
+
+def profile_read(kind: int):
+    """(total_ms, launches, max_ms) of the recorded launches of one kind."""
+    tot, mx = ctypes.c_double(), ctypes.c_double()
+    cnt = ctypes.c_int64()
+    check(lib().sinkhorn_profile_read(int(kind), ctypes.byref(tot),
+                                      ctypes.byref(cnt), ctypes.byref(mx)),
+          "sinkhorn_profile_read")
+    return tot.value, cnt.value, mx.value
+
+
 # ------------------------------------------------------------------ (a8)
 class _SinkhornDivergenceFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, X, Y, a, b, U, eps, q, tol, max_iter, fixed_iter):
-        out, state = divergence(X, Y, a, b, U, eps, q, tol, max_iter, fixed_iter)
+    def forward(ctx, X, Y, a, b, U, eps, q, tol, max_iter, fixed_iter, range):
+        out, state = divergence(X, Y, a, b, U, eps, q, tol, max_iter,
+                                fixed_iter, range)
         ctx.state = state
         return out[0]
 
@@ -303,12 +369,12 @@ class _SinkhornDivergenceFn(torch.autograd.Function):
         need = (ctx.needs_input_grad[0], ctx.needs_input_grad[2],
                 ctx.needs_input_grad[1], ctx.needs_input_grad[3])
         dX, da, dY, db = divergence_backward(ctx.state, g, need)
-        return dX, dY, da, db, None, None, None, None, None, None
+        return dX, dY, da, db, None, None, None, None, None, None, None
 
 
 def sinkhorn_divergence(X, Y, a, b, U, eps, q, tol=1e-6, max_iter=2000,
-                        fixed_iter=0):
+                        fixed_iter=0, range=EXTENDED):
     """Differentiable debiased Sinkhorn divergence (float64 scalar tensor);
     gradients flow to X, Y, a and b through the library's adjoint kernels."""
     return _SinkhornDivergenceFn.apply(X, Y, a, b, U, eps, q, tol, max_iter,
-                                       fixed_iter)
+                                       fixed_iter, range)

@@ -9,8 +9,12 @@
 // where (p, g) = (u~, Phi~_y^T v~) on the row side and (v~, Phi~_x^T u~) on
 // the column side.  The kernel evaluates up to three such terms with
 // coefficients in one read of each feature row:
-//   h_ik = sum_t c_t p^t_i g^t_k,  D_i = Phi~_i . h_i,  V_i = sum_k Phi~_ik h_ik u_k,
-//   dX_i (+)= grad_out * 4 (x_i D_i - V_i).
+//   h_ik = sum_t c_t p^t_i Phi~_ik g^t_k,  D_i = sum_k h_ik,
+//   V_i = sum_k h_ik u_k,   dX_i (+)= grad_out * 4 (x_i D_i - V_i).
+// In the extended-range domain Phi~_ik = 2^L_ik (log2 features) and p, g
+// are (exponent, mantissa) pairs, so each product p_i Phi~_ik g_k is formed
+// as M_p M_g 2^(E_p + L_ik + E_g); it is a share of transported mass and
+// stays in float32 range.
 //
 // Weight gradient (envelope theorem on Eq. eval-dual): dW/da = eps log u on
 // the row side; the dual optimum is unique up to a constant (App. B), so the
@@ -23,8 +27,8 @@
 namespace sk {
 namespace {
 
-constexpr int kAdjLdsFloats = 12288;
-constexpr int kDChunk = 8;  // coordinates reduced per round
+constexpr int kAdjUtFloats = 12288;  // transposed anchors when d*r fits
+constexpr int kDChunk = 8;           // coordinates reduced per round
 
 template <int G>
 __device__ __forceinline__ float gsum(float x) {
@@ -44,55 +48,100 @@ features_backward_kernel(const float* __restrict__ X, int64_t n, int d,
                          const float* __restrict__ p2, const float* __restrict__ g2, float c2,
                          const float* __restrict__ p3, const float* __restrict__ g3, float c3,
                          const float* __restrict__ grad_out, int accumulate,
+                         const int32_t* __restrict__ xr_flag, int xr_host,
                          float* __restrict__ dX) {
-  __shared__ float Ut[kAdjLdsFloats];
+  __shared__ float Ut[kAdjUtFloats];
+  // r-vectors: linear g_t at gv[t*R..], extended range E at gv[2t*R..],
+  // M at gv[(2t+1)*R..]
+  __shared__ float4 gv4[6 * G * C];
+  float* gv = reinterpret_cast<float*>(gv4);
+  constexpr int R = 4 * G * C;
   constexpr int RPW = 64 / G;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int sub = lane / G;
   const int cl = lane % G;
+  const bool xr = xr_flag ? (*xr_flag != 0) : (xr_host != 0);
   const int rp = (r + 3) & ~3;
-  const bool in_lds = (int64_t)d * rp <= kAdjLdsFloats;
+  const bool in_lds = (int64_t)d * rp <= kAdjUtFloats;
   if (in_lds) {
     for (int idx = threadIdx.x; idx < d * rp; idx += kBlock) {
       const int dim = idx / rp, k = idx - dim * rp;
       Ut[idx] = k < r ? U[(int64_t)k * d + dim] : 0.f;
     }
   }
-  __syncthreads();
-  float4 G1[C], G2[C], G3[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const int col = 4 * cl + 4 * G * c;
-    const bool cv = col < r;
-    G1[c] = (cv && g1) ? *reinterpret_cast<const float4*>(g1 + col) : f4z();
-    G2[c] = (cv && g2) ? *reinterpret_cast<const float4*>(g2 + col) : f4z();
-    G3[c] = (cv && g3) ? *reinterpret_cast<const float4*>(g3 + col) : f4z();
+  const float* gs[3] = {g1, g2, g3};
+  for (int t = 0; t < 3; ++t) {
+    for (int k = threadIdx.x; k < R; k += kBlock) {
+      const bool ok = gs[t] && k < r;
+      if (xr) {
+        gv[(2 * t) * R + k] = ok ? gs[t][k] : -1.0e30f;
+        gv[(2 * t + 1) * R + k] = ok ? gs[t][r + k] : 0.f;
+      } else {
+        gv[t * R + k] = ok ? gs[t][k] : 0.f;
+      }
+    }
   }
+  __syncthreads();
   const float go = 4.0f * (grad_out ? *grad_out : 1.0f);
   const int64_t rows_per_block_step = (int64_t)kWaves * RPW;
   for (int64_t base = (int64_t)blockIdx.x * rows_per_block_step; base < n;
        base += (int64_t)gridDim.x * rows_per_block_step) {
     const int64_t row = base + wave * RPW + sub;
     const bool rv = row < n;
-    const float q1 = (rv && p1) ? c1 * p1[row] : 0.f;
-    const float q2 = (rv && p2) ? c2 * p2[row] : 0.f;
-    const float q3 = (rv && p3) ? c3 * p3[row] : 0.f;
     float4 ph[C];
     float Dl = 0.f;
+    if (!xr) {
+      const float q1 = (rv && p1) ? c1 * p1[row] : 0.f;
+      const float q2 = (rv && p2) ? c2 * p2[row] : 0.f;
+      const float q3 = (rv && p3) ? c3 * p3[row] : 0.f;
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const int col = 4 * cl + 4 * G * c;
-      float4 x = (rv && col < r)
-                     ? *reinterpret_cast<const float4*>(Phi + row * (int64_t)r + col)
-                     : f4z();
-      float4 h;
-      h.x = q1 * G1[c].x + q2 * G2[c].x + q3 * G3[c].x;
-      h.y = q1 * G1[c].y + q2 * G2[c].y + q3 * G3[c].y;
-      h.z = q1 * G1[c].z + q2 * G2[c].z + q3 * G3[c].z;
-      h.w = q1 * G1[c].w + q2 * G2[c].w + q3 * G3[c].w;
-      ph[c] = make_float4(x.x * h.x, x.y * h.y, x.z * h.z, x.w * h.w);
-      Dl += (ph[c].x + ph[c].y) + (ph[c].z + ph[c].w);
+      for (int c = 0; c < C; ++c) {
+        const int col = 4 * cl + 4 * G * c;
+        float4 x = (rv && col < r)
+                       ? *reinterpret_cast<const float4*>(Phi + row * (int64_t)r + col)
+                       : f4z();
+        const float4 a1 = gv4[(0 * R + col) / 4];
+        const float4 a2 = gv4[(1 * R + col) / 4];
+        const float4 a3 = gv4[(2 * R + col) / 4];
+        float4 h;
+        h.x = q1 * a1.x + q2 * a2.x + q3 * a3.x;
+        h.y = q1 * a1.y + q2 * a2.y + q3 * a3.y;
+        h.z = q1 * a1.z + q2 * a2.z + q3 * a3.z;
+        h.w = q1 * a1.w + q2 * a2.w + q3 * a3.w;
+        ph[c] = make_float4(x.x * h.x, x.y * h.y, x.z * h.z, x.w * h.w);
+        Dl += (ph[c].x + ph[c].y) + (ph[c].z + ph[c].w);
+      }
+    } else {
+      const float* ps[3] = {p1, p2, p3};
+      const float cs[3] = {c1, c2, c3};
+      float pe[3], pm[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        pe[t] = (rv && ps[t]) ? ps[t][row] : 0.f;
+        pm[t] = (rv && ps[t]) ? cs[t] * ps[t][n + row] : 0.f;
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int col = 4 * cl + 4 * G * c;
+        const bool cv = rv && col < r;
+        const float4 L = cv ? *reinterpret_cast<const float4*>(Phi + row * (int64_t)r + col)
+                            : make_float4(-1.0e30f, -1.0e30f, -1.0e30f, -1.0e30f);
+        float4 h = f4z();
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const float4 ge = gv4[((2 * t) * R + col) / 4];
+          const float4 gm = gv4[((2 * t + 1) * R + col) / 4];
+          const float pet = pe[t], pmt = pm[t];
+          h.x = fmaf(pmt * gm.x, __builtin_amdgcn_exp2f(L.x + (pet + ge.x)), h.x);
+          h.y = fmaf(pmt * gm.y, __builtin_amdgcn_exp2f(L.y + (pet + ge.y)), h.y);
+          h.z = fmaf(pmt * gm.z, __builtin_amdgcn_exp2f(L.z + (pet + ge.z)), h.z);
+          h.w = fmaf(pmt * gm.w, __builtin_amdgcn_exp2f(L.w + (pet + ge.w)), h.w);
+        }
+        if (!cv) h = f4z();
+        ph[c] = h;
+        Dl += (h.x + h.y) + (h.z + h.w);
+      }
     }
     const float D = gsum<G>(Dl);
     for (int d0 = 0; d0 < d; d0 += kDChunk) {
@@ -146,17 +195,17 @@ typedef void (*AdjLaunch)(dim3, hipStream_t, const float*, int64_t, int,
                           const float*, int, const float*, const float*,
                           const float*, float, const float*, const float*,
                           float, const float*, const float*, float,
-                          const float*, int, float*);
+                          const float*, int, const int32_t*, int, float*);
 
 template <int G, int C>
 void launch_adj(dim3 grid, hipStream_t s, const float* X, int64_t n, int d,
                 const float* U, int r, const float* Phi, const float* p1,
                 const float* g1, float c1, const float* p2, const float* g2,
                 float c2, const float* p3, const float* g3, float c3,
-                const float* go, int acc, float* dX) {
+                const float* go, int acc, const int32_t* xf, int xh, float* dX) {
   hipLaunchKernelGGL((features_backward_kernel<G, C>), grid, dim3(kBlock), 0, s,
                      X, n, d, U, r, Phi, p1, g1, c1, p2, g2, c2, p3, g3, c3, go,
-                     acc, dX);
+                     acc, xf, xh, dX);
 }
 
 struct AdjClass {
@@ -175,16 +224,24 @@ const AdjClass kAdj[] = {
 };
 
 // ------------------------------------------------------------ weight grad
+__device__ __forceinline__ double log_scaling(const float* s, int64_t i,
+                                              int64_t n, bool xr) {
+  if (xr) return ((double)s[i] + log2((double)s[n + i])) * 0.69314718055994530942;
+  return log((double)s[i]);
+}
+
 __global__ void __launch_bounds__(kBlock)
 weight_grad_partial(const float* __restrict__ u1, const float* __restrict__ u2,
                     const float* __restrict__ u3, int64_t n, double eps,
+                    const int32_t* __restrict__ xr_flag,
                     double* __restrict__ part) {
   __shared__ double sh[kBlock];
+  const bool xr = xr_flag && *xr_flag != 0;
   double s = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kBlock) {
-    s += eps * (log((double)u1[i]) -
-                0.5 * (log((double)u2[i]) + log((double)u3[i])));
+    s += eps * (log_scaling(u1, i, n, xr) -
+                0.5 * (log_scaling(u2, i, n, xr) + log_scaling(u3, i, n, xr)));
   }
   sh[threadIdx.x] = s;
   __syncthreads();
@@ -198,9 +255,11 @@ weight_grad_partial(const float* __restrict__ u1, const float* __restrict__ u2,
 __global__ void __launch_bounds__(kBlock)
 weight_grad_final(const float* __restrict__ u1, const float* __restrict__ u2,
                   const float* __restrict__ u3, int64_t n, double eps,
+                  const int32_t* __restrict__ xr_flag,
                   const double* __restrict__ part, int nparts,
                   const float* __restrict__ grad_out, float* __restrict__ da) {
   __shared__ double sh[kBlock];
+  const bool xr = xr_flag && *xr_flag != 0;
   double s = 0.0;
   for (int i = threadIdx.x; i < nparts; i += kBlock) s += part[i];
   sh[threadIdx.x] = s;
@@ -213,8 +272,9 @@ weight_grad_final(const float* __restrict__ u1, const float* __restrict__ u2,
   const double go = grad_out ? (double)*grad_out : 1.0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kBlock) {
-    const double raw = eps * (log((double)u1[i]) -
-                              0.5 * (log((double)u2[i]) + log((double)u3[i])));
+    const double raw = eps * (log_scaling(u1, i, n, xr) -
+                              0.5 * (log_scaling(u2, i, n, xr) +
+                                     log_scaling(u3, i, n, xr)));
     da[i] = (float)(go * (raw - mean));
   }
 }
@@ -227,7 +287,8 @@ hipError_t launch_features_backward(const float* X, int64_t n, int d,
                                     const float* p2, const float* g2, float c2,
                                     const float* p3, const float* g3, float c3,
                                     const float* grad_out, int accumulate,
-                                    float* dX, hipStream_t s) {
+                                    const int32_t* xr_flag, int xr, float* dX,
+                                    hipStream_t s) {
   if (r % 4 != 0) return hipErrorInvalidValue;
   const AdjClass* cls = nullptr;
   for (const AdjClass& c : kAdj)
@@ -240,24 +301,29 @@ hipError_t launch_features_backward(const float* X, int64_t n, int d,
   int64_t grid = (n + rows_per_block - 1) / rows_per_block;
   if (grid > (int64_t)cus * 16) grid = (int64_t)cus * 16;
   if (grid < 1) grid = 1;
+  void* tok = prof_begin(kProfAdjoint, s);
   cls->launch(dim3((unsigned)grid), s, X, n, d, U, r, Phi, p1, g1, c1, p2, g2,
-              c2, p3, g3, c3, grad_out, accumulate, dX);
-  return hipGetLastError();
+              c2, p3, g3, c3, grad_out, accumulate, xr_flag, xr, dX);
+  const hipError_t e = hipGetLastError();
+  prof_end(tok, s);
+  return e;
 }
 
 hipError_t launch_weight_grad(const float* u1, const float* u2,
                               const float* u3, int64_t n, double eps,
-                              const float* grad_out, double* scratch,
-                              int scratch_blocks, float* da, hipStream_t s) {
+                              const float* grad_out, const int32_t* xr_flag,
+                              double* scratch, int scratch_blocks, float* da,
+                              hipStream_t s) {
   int64_t blocks = (n + kBlock - 1) / kBlock;
   if (blocks > scratch_blocks) blocks = scratch_blocks;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(weight_grad_partial, dim3((unsigned)blocks), dim3(kBlock),
-                     0, s, u1, u2, u3, n, eps, scratch);
+                     0, s, u1, u2, u3, n, eps, xr_flag, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(weight_grad_final, dim3((unsigned)blocks), dim3(kBlock), 0,
-                     s, u1, u2, u3, n, eps, scratch, (int)blocks, grad_out, da);
+                     s, u1, u2, u3, n, eps, xr_flag, scratch, (int)blocks,
+                     grad_out, da);
   return hipGetLastError();
 }
 

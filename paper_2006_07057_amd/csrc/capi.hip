@@ -94,6 +94,7 @@ int planned_group(int64_t n, int64_t m, int r) {
 int run_solves(const std::vector<SolveSpec>& specs, const sk_solve_opts* o,
                void* base, size_t cap, size_t* need, hipStream_t s) {
   Carver cv(base);
+  const int xr = o->range == SK_RANGE_EXTENDED ? 1 : 0;
   std::map<int, std::vector<int>> by_class;
   for (int i = 0; i < (int)specs.size(); ++i)
     by_class[class_rmax(specs[i].r)].push_back(i);
@@ -109,8 +110,10 @@ int run_solves(const std::vector<SolveSpec>& specs, const sk_solve_opts* o,
     max_sum_g = std::max(max_sum_g, sg);
     max_rmax = std::max(max_rmax, kv.first);
   }
+  // slots hold one partial r-vector per workgroup; pair layout [E | M] in
+  // the extended range, so the stride is 2 * rmax for both domains
   const int64_t slot_count = std::min<int64_t>(kMaxGroup, max_sum_g);
-  float* slots = cv.take<float>((size_t)slot_count * max_rmax);
+  float* slots = cv.take<float>((size_t)slot_count * 2 * max_rmax);
 
   struct ClassBufs {
     LaunchCtl* ctl;
@@ -132,8 +135,8 @@ int run_solves(const std::vector<SolveSpec>& specs, const sk_solve_opts* o,
     cb.dpart = cv.take<double>((size_t)sg * 4);
     bufs[kv.first] = cb;
     for (int i : kv.second) {
-      v2[i] = cv.take<float>((size_t)specs[i].m);
-      w2[i] = cv.take<float>((size_t)specs[i].r);
+      v2[i] = cv.take<float>(2 * (size_t)specs[i].m);
+      w2[i] = cv.take<float>(2 * (size_t)specs[i].r);
     }
   }
   if (need) *need = cv.off;
@@ -142,7 +145,7 @@ int run_solves(const std::vector<SolveSpec>& specs, const sk_solve_opts* o,
 
   for (auto& kv : by_class) {
     const int rmax = kv.first;
-    int capdev = solver_capacity(rmax);
+    int capdev = solver_capacity(rmax, xr);
     if (capdev <= 0) return SK_EHIP;
     capdev = std::min(capdev, kMaxGroup);
     std::vector<int> order = kv.second;
@@ -165,7 +168,7 @@ int run_solves(const std::vector<SolveSpec>& specs, const sk_solve_opts* o,
       D.srow = sp.srow; D.scol = sp.scol;
       D.u = sp.u; D.v = sp.v; D.v2 = v2[i]; D.w = sp.w; D.w2 = w2[i]; D.z = sp.z;
       D.slots = slots;
-      D.slot_stride = rmax;
+      D.slot_stride = 2 * rmax;
       D.members = cb.members + moff;
       D.dpart = cb.dpart + 4 * moff;
       D.bar = cb.bars + k;
@@ -184,7 +187,8 @@ int run_solves(const std::vector<SolveSpec>& specs, const sk_solve_opts* o,
     const int grid = std::min(capdev, seat);
     SK_HIP(upload_descs(cb.descs, descs.data(), (int)descs.size(), s));
     SK_HIP(launch_init_ctl(cb.ctl, cb.bars, (int)descs.size(), s));
-    SK_HIP(launch_solver(cb.descs, (int)descs.size(), rmax, seat, grid, cb.ctl, s));
+    SK_HIP(launch_solver(cb.descs, (int)descs.size(), rmax, xr, seat, grid,
+                         cb.ctl, s));
   }
   return SK_OK;
 }
@@ -194,8 +198,12 @@ struct AsmDesc {
   const sk_solve_info* info;  // three consecutive records: xy, xx, yy
   double* state_out;          // double[4] in the state (may be null)
   double* out;                // double[4] of the caller (may be null)
+  int32_t* meta;              // int32[4] in the state: [0] = numeric domain
+  int32_t xr;
+  int32_t pad;
 };
 
+// W_bar = W(mu,nu) - (W(mu,mu) + W(nu,nu)) / 2, Eq. (reg-sdiv), in float64.
 __global__ void assemble_kernel(const AsmDesc* descs, AsmDesc one, int count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
@@ -206,6 +214,18 @@ __global__ void assemble_kernel(const AsmDesc* descs, AsmDesc one, int count) {
     if (D.state_out) D.state_out[k] = vals[k];
     if (D.out) D.out[k] = vals[k];
   }
+  if (D.meta) {
+    D.meta[0] = D.xr;
+    D.meta[1] = 0;
+    D.meta[2] = 0;
+    D.meta[3] = 0;
+  }
+}
+
+// Records the numeric domain in a state before its features are computed,
+// so a backward pass always sees a defined flag.
+__global__ void set_meta_kernel(int32_t* meta, int32_t xr) {
+  if (threadIdx.x == 0) meta[0] = xr;
 }
 
 bool bad_ptr(const void* p) { return p == nullptr; }
@@ -229,6 +249,8 @@ int check_opts(const sk_solve_opts* o) {
   if (!(o->tol >= 0.0)) return SK_EINVAL;
   if (o->fixed_iter < 0) return SK_EINVAL;
   if (o->fixed_iter == 0 && o->max_iter < 1) return SK_EINVAL;
+  if (o->range != SK_RANGE_EXTENDED && o->range != SK_RANGE_LINEAR)
+    return SK_EINVAL;
   return SK_OK;
 }
 
@@ -243,15 +265,17 @@ void layout_of(int64_t n, int64_t m, int64_t r, sk_state_layout* L) {
   L->phiy = at(4 * (size_t)m * r);
   L->sx = at(4 * (size_t)n);
   L->sy = at(4 * (size_t)m);
+  // scalings and r-vectors are sized for the [E | M] pair layout
   const int64_t rows_u[3] = {n, n, m}, rows_v[3] = {m, n, m};
   for (int k = 0; k < 3; ++k) {
-    L->u[k] = at(4 * (size_t)rows_u[k]);
-    L->v[k] = at(4 * (size_t)rows_v[k]);
-    L->w[k] = at(4 * (size_t)r);
-    L->z[k] = at(4 * (size_t)r);
+    L->u[k] = at(8 * (size_t)rows_u[k]);
+    L->v[k] = at(8 * (size_t)rows_v[k]);
+    L->w[k] = at(8 * (size_t)r);
+    L->z[k] = at(8 * (size_t)r);
   }
   L->info = at(sizeof(sk_solve_info) * 3);
   L->out = at(sizeof(double) * 4);
+  L->meta = at(sizeof(int32_t) * 4);
   L->total = align_up(cv.off, 256);
 }
 
@@ -329,14 +353,16 @@ int sinkhorn_gaussian_q(double R, double eps, int64_t d, double* q_host) {
 }
 
 int sinkhorn_features(const float* X, int64_t n, int64_t d, const float* U,
-                      int64_t r, double eps, double q, float* Phi,
-                      float* logscale, sk_stream_t stream) {
+                      int64_t r, double eps, double q, int32_t range,
+                      float* Phi, float* logscale, sk_stream_t stream) {
   if (!X || !U || !Phi || !logscale || n < 1 || d < 1 || r < 1) return SK_EINVAL;
   if (!(eps > 0.0) || !(q > 0.5) || !isfinite(eps) || !isfinite(q))
     return SK_EINVAL;
+  if (range != SK_RANGE_EXTENDED && range != SK_RANGE_LINEAR) return SK_EINVAL;
   if (r > SK_MAX_R) return SK_ENOTSUP;
   if (d > (1 << 20) || n > (int64_t)1 << 40) return SK_EINVAL;
-  SK_HIP(launch_features(X, n, (int)d, U, (int)r, eps, q, Phi, logscale,
+  SK_HIP(launch_features(X, n, (int)d, U, (int)r, eps, q,
+                         range == SK_RANGE_EXTENDED ? 1 : 0, Phi, logscale,
                          S(stream)));
   return SK_OK;
 }
@@ -405,16 +431,21 @@ int sinkhorn_divergence(const sk_problem* p, const sk_solve_opts* opts,
   if (state_bytes < L.total) return SK_ENOMEM;
   if (ws_bytes < sinkhorn_divergence_workspace_size(p)) return SK_ENOMEM;
   hipStream_t s = S(stream);
+  const int xr = opts->range == SK_RANGE_EXTENDED ? 1 : 0;
+  hipLaunchKernelGGL(set_meta_kernel, dim3(1), dim3(64), 0, s,
+                     at<int32_t>(state, L.meta), xr);
+  SK_HIP(hipGetLastError());
   SK_HIP(launch_features(p->X, p->n, (int)p->d, p->U, (int)p->r, p->eps, p->q,
-                         at<float>(state, L.phix), at<float>(state, L.sx), s));
+                         xr, at<float>(state, L.phix), at<float>(state, L.sx), s));
   SK_HIP(launch_features(p->Y, p->m, (int)p->d, p->U, (int)p->r, p->eps, p->q,
-                         at<float>(state, L.phiy), at<float>(state, L.sy), s));
+                         xr, at<float>(state, L.phiy), at<float>(state, L.sy), s));
   std::vector<SolveSpec> specs;
   divergence_specs(p, state, &specs);
   size_t need = 0;
   rc = run_solves(specs, opts, ws, ws_bytes, &need, s);
   if (rc) return rc;
-  AsmDesc one{at<sk_solve_info>(state, L.info), at<double>(state, L.out), out};
+  AsmDesc one{at<sk_solve_info>(state, L.info), at<double>(state, L.out), out,
+              at<int32_t>(state, L.meta), xr, 0};
   hipLaunchKernelGGL(assemble_kernel, dim3(1), dim3(64), 0, s, nullptr, one, 1);
   SK_HIP(hipGetLastError());
   return SK_OK;
@@ -462,15 +493,16 @@ int sinkhorn_divergence_batched(const sk_problem* problems, int32_t count,
       tail + align_up(sizeof(FeatDesc) * 2 * (size_t)count, 256));
 
   // features: group the 2*count clouds by feature class, one launch each
+  const int xr = opts->range == SK_RANGE_EXTENDED ? 1 : 0;
   std::map<int, std::vector<FeatDesc>> fgroups;
   for (int i = 0; i < count; ++i) {
     const sk_problem& p = problems[i];
     sk_state_layout L;
     layout_of(p.n, p.m, p.r, &L);
     FeatDesc fx{p.X, p.U, at<float>(states[i], L.phix), at<float>(states[i], L.sx),
-                p.n, (int32_t)p.d, (int32_t)p.r, (float)p.eps, (float)p.q, 0};
+                p.n, (int32_t)p.d, (int32_t)p.r, (float)p.eps, (float)p.q, xr, 0, 0};
     FeatDesc fy{p.Y, p.U, at<float>(states[i], L.phiy), at<float>(states[i], L.sy),
-                p.m, (int32_t)p.d, (int32_t)p.r, (float)p.eps, (float)p.q, 0};
+                p.m, (int32_t)p.d, (int32_t)p.r, (float)p.eps, (float)p.q, xr, 0, 0};
     fgroups[class_rmax((int)p.r)].push_back(fx);
     fgroups[class_rmax((int)p.r)].push_back(fy);
   }
@@ -487,7 +519,8 @@ int sinkhorn_divergence_batched(const sk_problem* problems, int32_t count,
     sk_state_layout L;
     layout_of(p.n, p.m, p.r, &L);
     ad[i] = AsmDesc{at<sk_solve_info>(states[i], L.info),
-                    at<double>(states[i], L.out), out ? out + 4 * i : nullptr};
+                    at<double>(states[i], L.out), out ? out + 4 * i : nullptr,
+                    at<int32_t>(states[i], L.meta), xr, 0};
   }
   SK_HIP(upload_bytes(adev, ad.data(), sizeof(AsmDesc) * ad.size(), s));
   hipLaunchKernelGGL(assemble_kernel, dim3((count + 63) / 64), dim3(64), 0, s,
@@ -499,14 +532,17 @@ int sinkhorn_divergence_batched(const sk_problem* problems, int32_t count,
 int sinkhorn_features_backward(const float* X, int64_t n, int64_t d,
                                const float* U, int64_t r, const float* Phi,
                                const float* p, const float* g, float coef,
-                               int32_t accumulate, float* dX,
+                               int32_t accumulate, int32_t range, float* dX,
                                sk_stream_t stream) {
   if (!X || !U || !Phi || !p || !g || !dX || n < 1 || d < 1 || r < 1)
     return SK_EINVAL;
+  if (range != SK_RANGE_EXTENDED && range != SK_RANGE_LINEAR) return SK_EINVAL;
   if (r > SK_MAX_R || r % 4 != 0) return SK_ENOTSUP;
   SK_HIP(launch_features_backward(X, n, (int)d, U, (int)r, Phi, p, g, coef,
                                   nullptr, nullptr, 0.f, nullptr, nullptr, 0.f,
-                                  nullptr, accumulate, dX, S(stream)));
+                                  nullptr, accumulate, nullptr,
+                                  range == SK_RANGE_EXTENDED ? 1 : 0, dX,
+                                  S(stream)));
   return SK_OK;
 }
 
@@ -533,23 +569,25 @@ int sinkhorn_divergence_backward(const sk_problem* p, const void* state,
     z[k] = at<float>(state, L.z[k]);
   }
   const int r = (int)p->r, d = (int)p->d;
+  // the numeric domain recorded by the forward call, read on the device
+  const int32_t* xf = at<int32_t>(state, L.meta);
   if (dX)
     SK_HIP(launch_features_backward(p->X, p->n, d, p->U, r,
                                     at<float>(state, L.phix), u[0], w[0], 1.0f,
                                     u[1], w[1], -0.5f, v[1], z[1], -0.5f,
-                                    grad_out, 0, dX, s));
+                                    grad_out, 0, xf, 0, dX, s));
   if (dY)
     SK_HIP(launch_features_backward(p->Y, p->m, d, p->U, r,
                                     at<float>(state, L.phiy), v[0], z[0], 1.0f,
                                     u[2], w[2], -0.5f, v[2], z[2], -0.5f,
-                                    grad_out, 0, dY, s));
+                                    grad_out, 0, xf, 0, dY, s));
   double* scratch = static_cast<double*>(ws);
   const int half = (int)kBackwardScratchDoubles / 2;
   if (da)
-    SK_HIP(launch_weight_grad(u[0], u[1], v[1], p->n, p->eps, grad_out, scratch,
-                              half, da, s));
+    SK_HIP(launch_weight_grad(u[0], u[1], v[1], p->n, p->eps, grad_out, xf,
+                              scratch, half, da, s));
   if (db)
-    SK_HIP(launch_weight_grad(v[0], u[2], v[2], p->m, p->eps, grad_out,
+    SK_HIP(launch_weight_grad(v[0], u[2], v[2], p->m, p->eps, grad_out, xf,
                               scratch + half, half, db, s));
   return SK_OK;
 }

@@ -19,6 +19,7 @@ namespace sk {
 namespace {
 
 constexpr int kFeatLdsFloats = 12288;  // 48 KB of transposed anchors
+constexpr float kLog2e = 1.4426950408889634f;
 constexpr int kRowsPerWaveTile = 4;
 
 template <int G>
@@ -144,23 +145,32 @@ features_kernel(const FeatDesc* __restrict__ descs, int count, FeatDesc one,
       mx = group_max<G>(mx);
       if (rv) {
         float* orow = D.Phi + row * (int64_t)r;
+        // linear: exp(E - s) in (0, 1]; log2 output: (E - s) log2(e) <= 0
+        const bool lg = D.log2_out != 0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           const int col0 = VEC * cl + VEC * G * c;
           if constexpr (VEC == 4) {
             if (col0 < r) {
               float4 o;
-              o.x = expf(e[c][0] - mx);
-              o.y = expf(e[c][1] - mx);
-              o.z = expf(e[c][2] - mx);
-              o.w = expf(e[c][3] - mx);
+              if (lg) {
+                o.x = (e[c][0] - mx) * kLog2e;
+                o.y = (e[c][1] - mx) * kLog2e;
+                o.z = (e[c][2] - mx) * kLog2e;
+                o.w = (e[c][3] - mx) * kLog2e;
+              } else {
+                o.x = expf(e[c][0] - mx);
+                o.y = expf(e[c][1] - mx);
+                o.z = expf(e[c][2] - mx);
+                o.w = expf(e[c][3] - mx);
+              }
               *reinterpret_cast<float4*>(orow + col0) = o;
             }
           } else {
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
               const int col = col0 + v;
-              if (col < r) orow[col] = expf(e[c][v] - mx);
+              if (col < r) orow[col] = lg ? (e[c][v] - mx) * kLog2e : expf(e[c][v] - mx);
             }
           }
         }
@@ -236,17 +246,21 @@ int64_t feature_grid(int64_t tiles) {
 }  // namespace
 
 hipError_t launch_features(const float* X, int64_t n, int d, const float* U,
-                           int r, double eps, double q, float* Phi,
-                           float* logscale, hipStream_t s) {
+                           int r, double eps, double q, int log2_out,
+                           float* Phi, float* logscale, hipStream_t s) {
   const FeatClass* cls = feat_class(r);
   if (!cls) return hipErrorInvalidValue;
   FeatDesc one{};
   one.X = X; one.U = U; one.Phi = Phi; one.s = logscale;
   one.n = n; one.d = d; one.r = r;
   one.eps = (float)eps; one.q = (float)q; one.tile0 = 0;
+  one.log2_out = log2_out;
   const int64_t tiles = (n + cls->rows_per_tile - 1) / cls->rows_per_tile;
+  void* tok = prof_begin(kProfFeatures, s);
   cls->launch(dim3((unsigned)feature_grid(tiles)), s, nullptr, 1, one, tiles);
-  return hipGetLastError();
+  const hipError_t e = hipGetLastError();
+  prof_end(tok, s);
+  return e;
 }
 
 hipError_t launch_features_batched(const FeatDesc* host, int count,
@@ -267,9 +281,12 @@ hipError_t launch_features_batched(const FeatDesc* host, int count,
   const FeatDesc one = tmp[0];
   delete[] tmp;
   if (e != hipSuccess) return e;
+  void* tok = prof_begin(kProfFeatures, s);
   cls->launch(dim3((unsigned)feature_grid(tiles)), s, dev_scratch, count, one,
               tiles);
-  return hipGetLastError();
+  const hipError_t e2 = hipGetLastError();
+  prof_end(tok, s);
+  return e2;
 }
 
 int features_class_rmax(int r) {

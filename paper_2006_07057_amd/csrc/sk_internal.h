@@ -61,11 +61,9 @@ constexpr int kMaxGroup = 2048;
 int solver_class_rmax(int r);
 
 // Maximum number of co-resident workgroups of the solver for feature
-// count r on the current device (0 on error).
-int solver_capacity(int r);
-
-// Group size the scheduler gives a solve with these sizes.
-int solver_group_size(int64_t n, int64_t m, int r, int capacity);
+// count r (xr != 0: extended-range kernels) on the current device (0 on
+// error).
+int solver_capacity(int r, int xr);
 
 // Copy host bytes to device memory with stream-ordered kernel launches
 // (the bytes travel as kernel arguments), so the copy can be graph-captured
@@ -78,16 +76,17 @@ hipError_t upload_bytes(void* dev, const void* host, size_t nbytes,
 hipError_t upload_descs(SolveDesc* dev, const SolveDesc* host, int count,
                         hipStream_t s);
 
-// Run all solves in `dev_descs` (count entries, all with the same r class)
-// in one persistent launch.  total_seats = sum of g.
-hipError_t launch_solver(const SolveDesc* dev_descs, int count, int r,
+// Run all solves in `dev_descs` (count entries, all with the same r class
+// and numeric domain) in one persistent launch.  total_seats = sum of g.
+hipError_t launch_solver(const SolveDesc* dev_descs, int count, int r, int xr,
                          int total_seats, int grid, LaunchCtl* ctl,
                          hipStream_t s);
 
-// Features (row-scaled Gaussian positive features).
+// Features (row-scaled Gaussian positive features; log2 values when
+// log2_out != 0).
 hipError_t launch_features(const float* X, int64_t n, int d, const float* U,
-                           int r, double eps, double q, float* Phi,
-                           float* logscale, hipStream_t s);
+                           int r, double eps, double q, int log2_out,
+                           float* Phi, float* logscale, hipStream_t s);
 
 // Batched features over several (X, U) problems.
 struct FeatDesc {
@@ -98,31 +97,39 @@ struct FeatDesc {
   int64_t n;
   int32_t d, r;
   float eps, q;
+  int32_t log2_out;
+  int32_t pad;
   int64_t tile0;         // first row-tile index of this problem
 };
 hipError_t launch_features_batched(const FeatDesc* host, int count,
                                    FeatDesc* dev_scratch, hipStream_t s);
 
-// Divergence assembly: out[4*i..] from infos of solves (3 per problem).
-hipError_t launch_assemble(const sk_solve_info* const* infos_xy_xx_yy,
-                           double* const* outs, int count, hipStream_t s);
-
-// Adjoint kernels.
+// Adjoint kernels.  The numeric domain is read on the device from *xr_flag
+// (nonzero: extended range) when xr_flag is not null, else from xr.  In the
+// extended range a scaling p is [E(n) | M(n)] and an r-vector g is
+// [E(r) | M(r)].
 hipError_t launch_features_backward(const float* X, int64_t n, int d,
                                     const float* U, int r, const float* Phi,
                                     const float* p1, const float* g1, float c1,
                                     const float* p2, const float* g2, float c2,
                                     const float* p3, const float* g3, float c3,
                                     const float* grad_out, int accumulate,
-                                    float* dX, hipStream_t s);
+                                    const int32_t* xr_flag, int xr, float* dX,
+                                    hipStream_t s);
 hipError_t launch_weight_grad(const float* u1, const float* u2,
                               const float* u3, int64_t n, double eps,
-                              const float* grad_out, double* scratch,
-                              int scratch_blocks, float* da, hipStream_t s);
+                              const float* grad_out, const int32_t* xr_flag,
+                              double* scratch, int scratch_blocks, float* da,
+                              hipStream_t s);
 
 hipError_t launch_init_ctl(LaunchCtl* ctl, unsigned* bars, int nbars,
                            hipStream_t s);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Launch timing (see profile.hip).  Kinds: 0 solver, 1 features, 2 adjoint.
+enum { kProfSolver = 0, kProfFeatures = 1, kProfAdjoint = 2 };
+void* prof_begin(int kind, hipStream_t s);
+void prof_end(void* token, hipStream_t s);
 
 }  // namespace sk

@@ -17,6 +17,17 @@
 // extra read.  v and w are double-buffered so that the pair (u^(k), v^(k))
 // that passed the test is the one returned.
 //
+// Two numeric domains share that structure:
+//  * linear: features, scalings and r-vectors are plain float32 numbers.
+//    Fastest, but the scalings of well-separated clouds at small eps leave
+//    the float32 exponent range (reported as SK_ERANGE).
+//  * extended range: features are stored as log2 values, and every scaling
+//    and r-vector entry as a pair (integer exponent E, float32 mantissa M)
+//    meaning M * 2^E.  Sums are formed as float32 sums of M * 2^(x - shift)
+//    with an integer shift per row (dot side) or per column (accumulation,
+//    raised on the fly), so the relative precision is that of float32
+//    arithmetic while the range is unbounded in practice.
+//
 // The whole loop runs in one persistent launch.  Many independent solves
 // can share the launch: each solve owns `g` seats; a workgroup takes the next
 // free seat (atomic counter) and runs that solve together with the other
@@ -38,7 +49,10 @@ constexpr int MODE_UPDATE = 1;        // s_j = t/(p.z); acc += s_j p_j
 constexpr int MODE_UPDATE_CHECK = 2;  // as UPDATE + error of previous s
 constexpr int MODE_CHECK = 3;         // error of previous s only
 
+constexpr float kNegBig = -1.0e30f;   // "log of zero" sentinel (finite)
+
 __device__ __forceinline__ float4 f4zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+__device__ __forceinline__ float4 f4fill(float v) { return make_float4(v, v, v, v); }
 
 __device__ __forceinline__ void f4fma(float4& acc, float s, const float4& x) {
   acc.x = fmaf(s, x.x, acc.x);
@@ -55,13 +69,105 @@ __device__ __forceinline__ float f4dot(const float4& a, const float4& b, float t
   return t;
 }
 
-// Butterfly sum over groups of G consecutive lanes.  Addition is
-// commutative, so every lane of a group ends with bit-identical results.
+__device__ __forceinline__ float xexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float xldexp(float m, float e) {
+  // e is an integer-valued float; clamp keeps the conversion defined
+  return __builtin_amdgcn_ldexpf(m, (int)fmaxf(fminf(e, 512.f), -512.f));
+}
+
+// Butterfly reductions over groups of G consecutive lanes.  Addition and
+// max are commutative, so every lane of a group ends with bit-identical
+// results.
 template <int G>
 __device__ __forceinline__ float group_sum(float x) {
 #pragma unroll
   for (int off = 1; off < G; off <<= 1) x += __shfl_xor(x, off, 64);
   return x;
+}
+
+template <int G>
+__device__ __forceinline__ float group_max(float x) {
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+// ------------------------------------------------- DPP lane reductions
+// Reductions over groups of G consecutive lanes with data-parallel
+// primitives (no LDS round trips).  Within a 16-lane row: swap neighbours,
+// swap pairs (quad permutes), then mirror halves of 8 and of 16; every lane
+// of the group then holds the same value (commutative operations).  Across
+// rows (G = 32, 64) the row totals are chained with the row broadcasts and
+// read back from the last lane of each group.
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+constexpr int kDppBcast15 = 0x142;
+constexpr int kDppBcast31 = 0x143;
+
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ float dpp(float old, float src) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(
+      __float_as_int(old), __float_as_int(src), CTRL, ROWMASK, 0xf, false));
+}
+
+template <int G>
+__device__ __forceinline__ float dpp_sum(float x) {
+  if (G >= 2) x += dpp<kDppXor1>(0.f, x);
+  if (G >= 4) x += dpp<kDppXor2>(0.f, x);
+  if (G >= 8) x += dpp<kDppHalfMirror>(0.f, x);
+  if (G >= 16) x += dpp<kDppMirror>(0.f, x);
+  if (G >= 32) x += dpp<kDppBcast15, 0xa>(0.f, x);
+  if (G == 64) {
+    x += dpp<kDppBcast31, 0xc>(0.f, x);
+    x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+  } else if (G == 32) {
+    const float lo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 31));
+    const float hi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+    x = (threadIdx.x & 32) ? hi : lo;
+  }
+  return x;
+}
+
+template <int G>
+__device__ __forceinline__ float dpp_max(float x) {
+  if (G >= 2) x = fmaxf(x, dpp<kDppXor1>(x, x));
+  if (G >= 4) x = fmaxf(x, dpp<kDppXor2>(x, x));
+  if (G >= 8) x = fmaxf(x, dpp<kDppHalfMirror>(x, x));
+  if (G >= 16) x = fmaxf(x, dpp<kDppMirror>(x, x));
+  if (G >= 32) x = fmaxf(x, dpp<kDppBcast15, 0xa>(x, x));
+  if (G == 64) {
+    x = fmaxf(x, dpp<kDppBcast31, 0xc>(x, x));
+    x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+  } else if (G == 32) {
+    const float lo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 31));
+    const float hi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+    x = (threadIdx.x & 32) ? hi : lo;
+  }
+  return x;
+}
+
+// Global-address-space views: loads through them compile to global (not
+// flat) memory instructions.
+typedef float nfloat4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const float gfloat;
+typedef __attribute__((address_space(1))) const nfloat4 gnfloat4;
+__device__ __forceinline__ gfloat* gp(const float* p) { return (gfloat*)p; }
+__device__ __forceinline__ float gld(const float* p) { return *gp(p); }
+__device__ __forceinline__ float4 gld4(const float* p) {
+  const nfloat4 v = *(gnfloat4*)p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// (E1, M1) + (E2, M2) in the extended-range representation.
+__device__ __forceinline__ void xr_combine(float& E1, float& M1, float E2,
+                                           float M2) {
+  if (M2 == 0.f) return;
+  if (M1 == 0.f) { E1 = E2; M1 = M2; return; }
+  const float E = fmaxf(E1, E2);
+  M1 = xldexp(M1, E1 - E) + xldexp(M2, E2 - E);
+  E1 = E;
 }
 
 // ---------------------------------------------------------------- barrier
@@ -75,7 +181,7 @@ struct BarrierState {
 
 // All threads of the workgroup call this.  Returns false if the launch was
 // aborted (time-out here or elsewhere).
-__device__ bool group_barrier(BarrierState& B) {
+__device__ __forceinline__ bool group_barrier(BarrierState& B) {
   __shared__ int s_ok;
   __threadfence();  // release this thread's writes at device scope
   __syncthreads();
@@ -112,162 +218,6 @@ __device__ bool group_barrier(BarrierState& B) {
   return ok;
 }
 
-// ------------------------------------------------------------------ pass
-// One half-step over rows [lo, hi) of P (row stride r), as described at the
-// top of the file.  Lane layout: G lanes per row, each lane holding C float4
-// chunks at columns 4*(lane%G) + 4*G*c; 64/G rows per wave load; U loads in
-// flight per wave.
-template <int G, int C, int U, int MODE>
-__device__ __forceinline__ void half_step(
-    const float* __restrict__ P, int64_t lo, int64_t hi, int r,
-    const float4 (&vec)[C], const float* __restrict__ target,
-    const float* __restrict__ sold, float* __restrict__ snew,
-    float4 (&acc)[C], double& err, int& bad) {
-  constexpr int RPW = 64 / G;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int sub = lane / G;
-  const int cl = lane % G;
-  const int64_t step = (int64_t)kWaves * U * RPW;
-  for (int64_t base = lo + (int64_t)wave * U * RPW; base < hi; base += step) {
-    float4 x[U][C];
-    float tw[U];
-    float to[U];
-#pragma unroll
-    for (int uu = 0; uu < U; ++uu) {
-      const int64_t row = base + uu * RPW + sub;
-      const bool rv = row < hi;
-      const float* prow = P + row * (int64_t)r;
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const int col = 4 * cl + 4 * G * c;
-        x[uu][c] = (rv && col < r) ? *reinterpret_cast<const float4*>(prow + col)
-                                   : f4zero();
-      }
-      if (MODE == MODE_ACCUM) {
-        tw[uu] = rv ? (target ? target[row] : 1.0f) : 0.0f;
-      } else {
-        tw[uu] = rv ? target[row] : 0.0f;
-      }
-      if (MODE == MODE_UPDATE_CHECK || MODE == MODE_CHECK) {
-        to[uu] = rv ? sold[row] : 0.0f;
-      }
-    }
-#pragma unroll
-    for (int uu = 0; uu < U; ++uu) {
-      const int64_t row = base + uu * RPW + sub;
-      const bool rv = row < hi;
-      float coef = 0.0f;
-      if (MODE == MODE_ACCUM) {
-        coef = tw[uu];
-      } else {
-        float t = 0.0f;
-#pragma unroll
-        for (int c = 0; c < C; ++c) t = f4dot(x[uu][c], vec[c], t);
-        t = group_sum<G>(t);
-        if (MODE == MODE_UPDATE_CHECK || MODE == MODE_CHECK) {
-          if (rv && cl == 0)
-            err += fabs((double)to[uu] * (double)t - (double)tw[uu]);
-        }
-        if (MODE != MODE_CHECK) {
-          const float nv = tw[uu] / t;
-          if (rv) {
-            if (!(t > 0.0f) || !(nv > 0.0f) || !isfinite(nv)) bad = 1;
-            if (cl == 0) snew[row] = nv;
-          }
-          coef = rv ? nv : 0.0f;
-        } else {
-          if (rv && !(t > 0.0f)) bad = 1;
-        }
-      }
-      if (MODE != MODE_CHECK) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) f4fma(acc[c], coef, x[uu][c]);
-      }
-    }
-  }
-}
-
-// Sum the per-lane accumulators of the workgroup into one r-vector at out.
-template <int G, int C>
-__device__ __forceinline__ void block_reduce_store(float4 (&acc)[C],
-                                                   float* __restrict__ out,
-                                                   int r, float4* lds) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int off = G; off < 64; off <<= 1) {
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      acc[c].x += __shfl_xor(acc[c].x, off, 64);
-      acc[c].y += __shfl_xor(acc[c].y, off, 64);
-      acc[c].z += __shfl_xor(acc[c].z, off, 64);
-      acc[c].w += __shfl_xor(acc[c].w, off, 64);
-    }
-  }
-  const int r4 = r >> 2;
-  if (lane < G) {
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const int c4 = lane + G * c;
-      if (c4 < r4) lds[wave * r4 + c4] = acc[c];
-    }
-  }
-  __syncthreads();
-  for (int c4 = threadIdx.x; c4 < r4; c4 += kBlock) {
-    float4 s = lds[c4];
-#pragma unroll
-    for (int w = 1; w < kWaves; ++w) {
-      const float4 t = lds[w * r4 + c4];
-      s.x += t.x; s.y += t.y; s.z += t.z; s.w += t.w;
-    }
-    reinterpret_cast<float4*>(out)[c4] = s;
-  }
-  __syncthreads();
-}
-
-// Workgroup `br` of a group of g sums its slice of float4 columns over the g
-// workgroup partials (fixed order: by seat) and writes the result to out.
-__device__ __forceinline__ void column_reduce(const float* __restrict__ slots,
-                                              int slot_stride,
-                                              const int32_t* __restrict__ members,
-                                              int g, int r, int br,
-                                              float* __restrict__ out,
-                                              float4* lds) {
-  const int r4 = r >> 2;
-  const int per = (r4 + g - 1) / g;
-  const int c0 = br * per;
-  const int c1 = min(r4, c0 + per);
-  float4* o4 = reinterpret_cast<float4*>(out);
-  for (int cc = c0; cc < c1; cc += kBlock) {
-    const int nc = min(kBlock, c1 - cc);
-    const int S = kBlock / nc;
-    const int t = threadIdx.x;
-    const int col = cc + t % nc;
-    const int split = t / nc;
-    float4 s = f4zero();
-    if (split < S) {
-      for (int b = split; b < g; b += S) {
-        const float4* p4 = reinterpret_cast<const float4*>(
-            slots + (int64_t)members[b] * slot_stride);
-        const float4 v = p4[col];
-        s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
-      }
-    }
-    lds[t] = s;
-    __syncthreads();
-    if (t < nc) {
-      float4 tot = lds[t];
-      for (int k = 1; k < S; ++k) {
-        const float4 v = lds[t + k * nc];
-        tot.x += v.x; tot.y += v.y; tot.z += v.z; tot.w += v.w;
-      }
-      o4[col] = tot;
-    }
-    __syncthreads();
-  }
-}
-
 // Sum of g float64 values, identical in every workgroup (fixed order).
 __device__ __forceinline__ double group_dsum(const double* __restrict__ src,
                                              int g, double* lds) {
@@ -296,45 +246,576 @@ __device__ __forceinline__ double block_dsum(double v, double* lds) {
   return res;
 }
 
-template <int G, int C>
-__device__ __forceinline__ void load_vec(const float* __restrict__ src, int r,
-                                         float4 (&vec)[C]) {
-  const int cl = (threadIdx.x & 63) % G;
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const int col = 4 * cl + 4 * G * c;
-    vec[c] = col < r ? *reinterpret_cast<const float4*>(src + col) : f4zero();
-  }
-}
+// ================================================================ linear
+// Lane layout: G lanes per row, each lane holding C float4 chunks at
+// columns 4*(lane%G) + 4*G*c; 64/G rows per wave load; U loads in flight.
+template <int G, int C, int U>
+struct LinearDomain {
+  static constexpr int kLdsFloats = 4 * ((kWaves * G * C) > kBlock ? (kWaves * G * C) : kBlock);
+  static constexpr int kVecStride = 1;  // floats per r-vector entry
+  // occupancy target (waves per SIMD) that bounds the register budget
+  static constexpr int kWavesPerEU = C <= 2 ? 4 : (C <= 4 ? 3 : (C <= 8 ? 2 : 1));
+  static constexpr int kRowStride = 1;  // floats per scaling entry
 
-template <int C>
-__device__ __forceinline__ void zero_acc(float4 (&acc)[C]) {
+  struct State {
+    float4 vec[C];
+    float4 acc[C];
+  };
+
+  __device__ __forceinline__ static void zero(State& S) {
 #pragma unroll
-  for (int c = 0; c < C; ++c) acc[c] = f4zero();
-}
+    for (int c = 0; c < C; ++c) S.acc[c] = f4zero();
+  }
+
+  // src: r floats
+  __device__ __forceinline__ static void load_vec(const float* __restrict__ src, int r,
+                                  State& S, float* lds) {
+    const int cl = (threadIdx.x & 63) % G;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int col = 4 * cl + 4 * G * c;
+      S.vec[c] = col < r ? *reinterpret_cast<const float4*>(src + col) : f4zero();
+    }
+  }
+
+  // sold/snew/target index rows; scalings are single floats.
+  template <int MODE>
+  __device__ __forceinline__ static void half_step(const float* __restrict__ P, int64_t lo,
+                                   int64_t hi, int r, int64_t nrows,
+                                   State& S, const float* __restrict__ target,
+                                   const float* __restrict__ sold,
+                                   float* __restrict__ snew, double& err,
+                                   int& bad, const float* lds) {
+    constexpr int RPW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sub = lane / G;
+    const int cl = lane % G;
+    const int64_t step = (int64_t)kWaves * U * RPW;
+
+    // Rows past `hi` load row hi-1 (always valid) and are neutralised with a
+    // zero coefficient; masked columns meet a zero entry of the r-vector and
+    // their accumulators are never stored.  No load is conditional.
+    // Addresses: a wave-uniform base per batch (scalar registers) plus a
+    // small 32-bit per-lane offset.
+    struct Batch {
+      float4 x[U][C];
+      float tw[U];
+      float to[U];
+    };
+    int coff[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int col = 4 * cl + 4 * G * c;
+      coff[c] = col < r ? col : 0;
+    }
+    auto load = [&](Batch& B, int64_t base) {
+      const float* pb = P + base * (int64_t)r;
+      const int64_t rem64 = hi - base;
+      const int rem = rem64 < U * RPW ? (int)rem64 : U * RPW;
+#pragma unroll
+      for (int uu = 0; uu < U; ++uu) {
+        const int rr = uu * RPW + sub;
+        const int rc = rr < rem ? rr : rem - 1;
+        const float* prow = pb + rc * r;
+#pragma unroll
+        for (int c = 0; c < C; ++c) B.x[uu][c] = gld4(prow + coff[c]);
+        if (MODE == MODE_ACCUM) {
+          B.tw[uu] = sold ? gld(sold + base + rc) : 1.0f;
+        } else {
+          B.tw[uu] = gld(target + base + rc);
+        }
+        if (MODE == MODE_UPDATE_CHECK || MODE == MODE_CHECK)
+          B.to[uu] = gld(sold + base + rc);
+      }
+    };
+    auto process = [&](const Batch& B, int64_t base) {
+      const int64_t rem = hi - base;
+#pragma unroll
+      for (int uu = 0; uu < U; ++uu) {
+        const int rr = uu * RPW + sub;
+        const int64_t row = base + rr;
+        const bool rv = rr < rem;
+        float coef = 0.0f;
+        if (MODE == MODE_ACCUM) {
+          coef = rv ? B.tw[uu] : 0.0f;
+        } else {
+          float t = 0.0f;
+#pragma unroll
+          for (int c = 0; c < C; ++c) t = f4dot(B.x[uu][c], S.vec[c], t);
+          t = dpp_sum<G>(t);
+          if (MODE == MODE_UPDATE_CHECK || MODE == MODE_CHECK) {
+            if (rv && cl == 0)
+              err += fabs((double)B.to[uu] * (double)t - (double)B.tw[uu]);
+          }
+          if (MODE != MODE_CHECK) {
+            const float nv = B.tw[uu] / t;
+            if (rv) {
+              if (!(t > 0.0f) || !(nv > 0.0f) || !isfinite(nv)) bad = 1;
+              if (cl == 0) snew[row] = nv;
+            }
+            coef = rv ? nv : 0.0f;
+          } else {
+            if (rv && !(t > 0.0f)) bad = 1;
+          }
+        }
+        if (MODE != MODE_CHECK) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) f4fma(S.acc[c], coef, B.x[uu][c]);
+        }
+      }
+    };
+    // software pipeline: the next batch is in flight while one is processed
+    int64_t base = lo + (int64_t)wave * U * RPW;
+    if (base >= hi) return;
+    Batch A, Bb;
+    load(A, base);
+    for (;;) {
+      int64_t nb = base + step;
+      if (nb < hi) load(Bb, nb);
+      process(A, base);
+      if (nb >= hi) break;
+      base = nb;
+      nb = base + step;
+      if (nb < hi) load(A, nb);
+      process(Bb, base);
+      if (nb >= hi) break;
+      base = nb;
+    }
+  }
+
+  // Sum the per-lane accumulators of the workgroup into out (r floats).
+  __device__ __forceinline__ static void block_store(State& S, float* __restrict__ out, int r,
+                                     float* ldsf) {
+    float4* lds = reinterpret_cast<float4*>(ldsf);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+    for (int off = G; off < 64; off <<= 1) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        S.acc[c].x += __shfl_xor(S.acc[c].x, off, 64);
+        S.acc[c].y += __shfl_xor(S.acc[c].y, off, 64);
+        S.acc[c].z += __shfl_xor(S.acc[c].z, off, 64);
+        S.acc[c].w += __shfl_xor(S.acc[c].w, off, 64);
+      }
+    }
+    const int r4 = r >> 2;
+    __syncthreads();
+    if (lane < G) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int c4 = lane + G * c;
+        if (c4 < r4) lds[wave * r4 + c4] = S.acc[c];
+      }
+    }
+    __syncthreads();
+    for (int c4 = threadIdx.x; c4 < r4; c4 += kBlock) {
+      float4 s = lds[c4];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) {
+        const float4 t = lds[w * r4 + c4];
+        s.x += t.x; s.y += t.y; s.z += t.z; s.w += t.w;
+      }
+      reinterpret_cast<float4*>(out)[c4] = s;
+    }
+    __syncthreads();
+  }
+
+  // Workgroup br of a group of g sums its slice of float4 columns over the
+  // g workgroup partials (fixed order: by seat) and writes them to out.
+  __device__ __forceinline__ static void column_reduce(const float* __restrict__ slots,
+                                       int slot_stride,
+                                       const int32_t* __restrict__ members,
+                                       int g, int r, int br,
+                                       float* __restrict__ out, float* ldsf) {
+    float4* lds = reinterpret_cast<float4*>(ldsf);
+    const int r4 = r >> 2;
+    const int per = (r4 + g - 1) / g;
+    const int c0 = br * per;
+    const int c1 = min(r4, c0 + per);
+    float4* o4 = reinterpret_cast<float4*>(out);
+    for (int cc = c0; cc < c1; cc += kBlock) {
+      const int nc = min(kBlock, c1 - cc);
+      const int Sn = kBlock / nc;
+      const int t = threadIdx.x;
+      const int col = cc + t % nc;
+      const int split = t / nc;
+      float4 s = f4zero();
+      if (split < Sn) {
+        for (int b = split; b < g; b += Sn) {
+          const float4* p4 = reinterpret_cast<const float4*>(
+              slots + (int64_t)members[b] * slot_stride);
+          const float4 v = p4[col];
+          s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+        }
+      }
+      lds[t] = s;
+      __syncthreads();
+      if (t < nc) {
+        float4 tot = lds[t];
+        for (int k = 1; k < Sn; ++k) {
+          const float4 v = lds[t + k * nc];
+          tot.x += v.x; tot.y += v.y; tot.z += v.z; tot.w += v.w;
+        }
+        o4[col] = tot;
+      }
+      __syncthreads();
+    }
+  }
+
+  // natural log of a stored scaling
+  __device__ __forceinline__ static double log_scaling(const float* s, int64_t i, int64_t) {
+    return log((double)s[i]);
+  }
+  __device__ __forceinline__ static void copy_scaling(const float* src, float* dst, int64_t i,
+                                      int64_t) {
+    dst[i] = src[i];
+  }
+};
+
+// ======================================================== extended range
+template <int G, int C, int U>
+struct XRangeDomain {
+  // LDS: the r-vector (2r floats) during a pass, then the workgroup
+  // reduction buffer (kWaves x r pairs).
+  static constexpr int kR = 4 * G * C;
+  static constexpr int kLdsFloats =
+      (2 * kWaves * kR) > (4 * kBlock) ? (2 * kWaves * kR) : (4 * kBlock);
+  static constexpr int kVecStride = 2;
+  static constexpr int kWavesPerEU = C <= 2 ? 3 : (C <= 4 ? 2 : 1);
+  static constexpr int kRowStride = 2;
+
+  struct State {
+    float4 accE[C];
+    float4 accM[C];
+  };
+
+  __device__ __forceinline__ static void zero(State& S) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      S.accE[c] = f4fill(kNegBig);
+      S.accM[c] = f4zero();
+    }
+  }
+
+  // src: [E(r) | M(r)] -> LDS as [E(kR) | M(kR)], padded with zero entries
+  // (E = kNegBig, M = 0) so every lane column has a defined value.
+  __device__ __forceinline__ static void load_vec(const float* __restrict__ src, int r,
+                                  State&, float* lds) {
+    __syncthreads();
+    gfloat* s = gp(src);
+    for (int i = threadIdx.x; i < kR; i += kBlock) {
+      const bool ok = i < r;
+      lds[i] = ok ? s[i] : kNegBig;
+      lds[kR + i] = ok ? s[r + i] : 0.f;
+    }
+    __syncthreads();
+  }
+
+  // acc_k += rowM * 2^(rowE + x_k) for the lane's columns.  The column
+  // exponent starts at the first valid row (exactly, from ceil(x_k)) and is
+  // raised when a term would exceed 2^0 relative to it; invalid rows come
+  // with rowE = kNegBig, rowM = 0 and add nothing.
+  __device__ __forceinline__ static void accum_row(State& S, const float4 (&x)[C],
+                                                   float rowE, float rowM,
+                                                   bool rv, bool& started) {
+    if (!started) {
+      if (!rv) return;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        float* E = reinterpret_cast<float*>(&S.accE[c]);
+        float* M = reinterpret_cast<float*>(&S.accM[c]);
+        const float* xv = reinterpret_cast<const float*>(&x[c]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float ce = ceilf(xv[q]);
+          E[q] = rowE + ce;
+          M[q] = xexp2(xv[q] - ce) * rowM;
+        }
+      }
+      started = true;
+      return;
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      float* E = reinterpret_cast<float*>(&S.accE[c]);
+      float* M = reinterpret_cast<float*>(&S.accM[c]);
+      const float* xv = reinterpret_cast<const float*>(&x[c]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float xx = xv[q] + (rowE - E[q]);
+        if (xx > 0.f) {  // raise the column exponent (rare after warm-up)
+          const float cc = ceilf(xx);
+          M[q] = xldexp(M[q], -cc);
+          E[q] += cc;
+          xx -= cc;
+        }
+        M[q] = fmaf(xexp2(xx), rowM, M[q]);
+      }
+    }
+  }
+
+  // sold: [E(nrows) | M(nrows)] previous scaling (CHECK modes) or warm
+  // start (ACCUM); snew: [E | M] new scaling.  target: linear weights.
+  template <int MODE>
+  __device__ __forceinline__ static void half_step(const float* __restrict__ P, int64_t lo,
+                                   int64_t hi, int r, int64_t nrows, State& S,
+                                   const float* __restrict__ target,
+                                   const float* __restrict__ sold,
+                                   float* __restrict__ snew, double& err,
+                                   int& bad, const float* lds) {
+    constexpr int RPW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sub = lane / G;
+    const int cl = lane % G;
+    const float* vE = lds;
+    const float* vM = lds + kR;
+    const int64_t step = (int64_t)kWaves * U * RPW;
+
+    bool started = false;
+    // Loads are unconditional: rows past `hi` read row hi-1, masked columns
+    // read column 0; both are neutralised afterwards (zero weight, or the
+    // padded r-vector entry 2^kNegBig * 0).  Addresses: wave-uniform batch
+    // base plus a small 32-bit per-lane offset.
+    struct Batch {
+      float4 x[U][C];
+      float tw[U], toE[U], toM[U];
+    };
+    int coff[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int col = 4 * cl + 4 * G * c;
+      coff[c] = col < r ? col : 0;
+    }
+    auto load = [&](Batch& B, int64_t base) {
+      const float* pb = P + base * (int64_t)r;
+      const int64_t rem64 = hi - base;
+      const int rem = rem64 < U * RPW ? (int)rem64 : U * RPW;
+#pragma unroll
+      for (int uu = 0; uu < U; ++uu) {
+        const int rr = uu * RPW + sub;
+        const int rc = rr < rem ? rr : rem - 1;
+        const float* prow = pb + rc * r;
+#pragma unroll
+        for (int c = 0; c < C; ++c) B.x[uu][c] = gld4(prow + coff[c]);
+        if (MODE == MODE_ACCUM) {
+          B.toE[uu] = sold ? gld(sold + base + rc) : 0.0f;
+          B.toM[uu] = sold ? gld(sold + nrows + base + rc) : 1.0f;
+        } else {
+          B.tw[uu] = gld(target + base + rc);
+          if (MODE == MODE_UPDATE_CHECK || MODE == MODE_CHECK) {
+            B.toE[uu] = gld(sold + base + rc);
+            B.toM[uu] = gld(sold + nrows + base + rc);
+          }
+        }
+      }
+    };
+    auto process = [&](const Batch& B, int64_t base) {
+      const int64_t rem = hi - base;
+#pragma unroll
+      for (int uu = 0; uu < U; ++uu) {
+        const int rr = uu * RPW + sub;
+        const int64_t row = base + rr;
+        const bool rv = rr < rem;
+        float rowE = kNegBig, rowM = 0.f;
+        if (MODE == MODE_ACCUM) {
+          if (rv) {
+            rowE = B.toE[uu];
+            rowM = B.toM[uu];
+          }
+        } else {
+          // dot side: t = sum_k 2^(x_k + zE_k) zM_k = 2^mx * ssum
+          float mx = kNegBig;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const int col = 4 * cl + 4 * G * c;
+            const float4 e4 = *reinterpret_cast<const float4*>(vE + col);
+            const float4& xv = B.x[uu][c];
+            mx = fmaxf(mx, fmaxf(fmaxf(xv.x + e4.x, xv.y + e4.y),
+                                 fmaxf(xv.z + e4.z, xv.w + e4.w)));
+          }
+          mx = ceilf(dpp_max<G>(mx));
+          float ssum = 0.f;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const int col = 4 * cl + 4 * G * c;
+            const float4 e4 = *reinterpret_cast<const float4*>(vE + col);
+            const float4 m4 = *reinterpret_cast<const float4*>(vM + col);
+            const float4& xv = B.x[uu][c];
+            ssum = fmaf(xexp2(xv.x + (e4.x - mx)), m4.x, ssum);
+            ssum = fmaf(xexp2(xv.y + (e4.y - mx)), m4.y, ssum);
+            ssum = fmaf(xexp2(xv.z + (e4.z - mx)), m4.z, ssum);
+            ssum = fmaf(xexp2(xv.w + (e4.w - mx)), m4.w, ssum);
+          }
+          ssum = dpp_sum<G>(ssum);
+          if (MODE == MODE_UPDATE_CHECK || MODE == MODE_CHECK) {
+            if (rv && cl == 0) {
+              const double prod = (double)B.toM[uu] * (double)ssum;
+              const double ex = (double)B.toE[uu] + (double)mx;
+              err += fabs(ldexp(prod, (int)fmax(fmin(ex, 2000.0), -2000.0)) -
+                          (double)B.tw[uu]);
+            }
+          }
+          if (MODE != MODE_CHECK) {
+            const float nm = B.tw[uu] / ssum;
+            const float ne = -mx;
+            if (rv) {
+              if (!(ssum > 0.0f) || !(nm > 0.0f) || !isfinite(nm) ||
+                  !(mx > -1.0e7f) || !(mx < 1.0e7f))
+                bad = 1;
+              if (cl == 0) {
+                snew[row] = ne;
+                snew[nrows + row] = nm;
+              }
+              rowE = ne;
+              rowM = nm;
+            }
+          } else {
+            if (rv && !(ssum > 0.0f)) bad = 1;
+          }
+        }
+        if (MODE != MODE_CHECK) accum_row(S, B.x[uu], rowE, rowM, rv, started);
+      }
+    };
+    int64_t base = lo + (int64_t)wave * U * RPW;
+    if (base >= hi) return;
+    Batch A, Bb;
+    load(A, base);
+    for (;;) {
+      int64_t nb = base + step;
+      if (nb < hi) load(Bb, nb);
+      process(A, base);
+      if (nb >= hi) break;
+      base = nb;
+      nb = base + step;
+      if (nb < hi) load(A, nb);
+      process(Bb, base);
+      if (nb >= hi) break;
+      base = nb;
+    }
+  }
+
+  // Combine the lanes' (E, M) accumulators into out = [E(r) | M(r)].
+  __device__ __forceinline__ static void block_store(State& S, float* __restrict__ out, int r,
+                                     float* lds) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+    for (int off = G; off < 64; off <<= 1) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        float* E = reinterpret_cast<float*>(&S.accE[c]);
+        float* M = reinterpret_cast<float*>(&S.accM[c]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float oe = __shfl_xor(E[q], off, 64);
+          const float om = __shfl_xor(M[q], off, 64);
+          // order the operands so both lanes compute the same value
+          float e1 = E[q], m1 = M[q], e2 = oe, m2 = om;
+          if ((lane & off) != 0) { e1 = oe; m1 = om; e2 = E[q]; m2 = M[q]; }
+          xr_combine(e1, m1, e2, m2);
+          E[q] = e1;
+          M[q] = m1;
+        }
+      }
+    }
+    __syncthreads();  // the r-vector in LDS is no longer needed
+    if (lane < G) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int col = 4 * lane + 4 * G * c;
+        if (col < r) {
+          *reinterpret_cast<float4*>(lds + (2 * wave) * r + col) = S.accE[c];
+          *reinterpret_cast<float4*>(lds + (2 * wave + 1) * r + col) = S.accM[c];
+        }
+      }
+    }
+    __syncthreads();
+    for (int col = threadIdx.x; col < r; col += kBlock) {
+      float e = lds[col], m = lds[r + col];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w)
+        xr_combine(e, m, lds[(2 * w) * r + col], lds[(2 * w + 1) * r + col]);
+      out[col] = e;
+      out[r + col] = m;
+    }
+    __syncthreads();
+  }
+
+  __device__ __forceinline__ static void column_reduce(const float* __restrict__ slots,
+                                       int slot_stride,
+                                       const int32_t* __restrict__ members,
+                                       int g, int r, int br,
+                                       float* __restrict__ out, float* lds) {
+    const int per = (r + g - 1) / g;
+    const int c0 = br * per;
+    const int c1 = min(r, c0 + per);
+    for (int cc = c0; cc < c1; cc += kBlock) {
+      const int nc = min(kBlock, c1 - cc);
+      const int Sn = kBlock / nc;
+      const int t = threadIdx.x;
+      const int col = cc + t % nc;
+      const int split = t / nc;
+      float e = kNegBig, m = 0.f;
+      if (split < Sn) {
+        for (int b = split; b < g; b += Sn) {
+          const float* p = slots + (int64_t)members[b] * slot_stride;
+          xr_combine(e, m, p[col], p[r + col]);
+        }
+      }
+      lds[t] = e;
+      lds[kBlock + t] = m;
+      __syncthreads();
+      if (t < nc) {
+        float te = lds[t], tm = lds[kBlock + t];
+        for (int k = 1; k < Sn; ++k)
+          xr_combine(te, tm, lds[t + k * nc], lds[kBlock + t + k * nc]);
+        if (tm > 0.f) {  // normalise the mantissa to [0.5, 1)
+          int ex = 0;
+          tm = frexpf(tm, &ex);
+          te += (float)ex;
+        } else {
+          te = kNegBig;
+        }
+        out[col] = te;
+        out[r + col] = tm;
+      }
+      __syncthreads();
+    }
+  }
+
+  __device__ __forceinline__ static double log_scaling(const float* s, int64_t i, int64_t n) {
+    return ((double)s[i] + log2((double)s[n + i])) * 0.69314718055994530942;
+  }
+  __device__ __forceinline__ static void copy_scaling(const float* src, float* dst, int64_t i,
+                                      int64_t n) {
+    dst[i] = src[i];
+    dst[n + i] = src[n + i];
+  }
+};
 
 struct Shared {
   double d[kBlock];
 };
 
 // Reduce a half-step's accumulators into dst (directly when g == 1, else via
-// block partials + barrier + column slice), publish (err, bad) and return
-// the group totals through err/bad.  Returns false if aborted.
-template <int G, int C>
+// workgroup partials + barrier + column slice), publish (err, bad) and
+// return the group totals through err/bad.  Returns false if aborted.
+template <class Dom>
 __device__ __forceinline__ bool finish_half_step(
-    const SolveDesc& D, int br, BarrierState& B, float4 (&acc)[C],
+    const SolveDesc& D, int br, BarrierState& B, typename Dom::State& S,
     float* __restrict__ dst, bool reduce_vec, double& err, int& bad,
-    float4* lds_vec, Shared& sh) {
+    float* lds, Shared& sh) {
   const int g = D.g;
-  // Per-workgroup totals of the scalar partials.
   const double e_blk = block_dsum(err, sh.d);
   const double b_blk = block_dsum((double)bad, sh.d);
   if (reduce_vec) {
     if (g == 1) {
-      block_reduce_store<G, C>(acc, dst, D.r, lds_vec);
+      Dom::block_store(S, dst, D.r, lds);
     } else {
-      block_reduce_store<G, C>(acc, D.slots + (int64_t)blockIdx.x * D.slot_stride,
-                               D.r, lds_vec);
+      Dom::block_store(S, D.slots + (int64_t)blockIdx.x * D.slot_stride, D.r, lds);
     }
   }
   if (threadIdx.x == 0) {
@@ -344,7 +825,7 @@ __device__ __forceinline__ bool finish_half_step(
   if (!group_barrier(B)) return false;
   if (g > 1) {
     if (reduce_vec)
-      column_reduce(D.slots, D.slot_stride, D.members, g, D.r, br, dst, lds_vec);
+      Dom::column_reduce(D.slots, D.slot_stride, D.members, g, D.r, br, dst, lds);
     err = group_dsum(D.dpart, g, sh.d);
     bad = group_dsum(D.dpart + g, g, sh.d) > 0.0 ? 1 : 0;
     if (!group_barrier(B)) return false;
@@ -355,58 +836,85 @@ __device__ __forceinline__ bool finish_half_step(
   return true;
 }
 
-template <int G, int C, int U>
-__device__ void run_solve(const SolveDesc& D, int br, LaunchCtl* ctl,
-                          uint64_t tlimit, float4* lds_vec, Shared& sh) {
-  const int g = D.g;
-  const int r = D.r;
-  BarrierState B{D.bar, &ctl->abort_flag, 0u, (unsigned)g, tlimit};
-  const int64_t rlo = D.n * br / g, rhi = D.n * (br + 1) / g;
-  const int64_t clo = D.m * br / g, chi = D.m * (br + 1) / g;
-  float* vbuf[2] = {D.v2, D.v};
-  float* wbuf[2] = {D.w2, D.w};
+// Wave-uniform copies of values read from LDS: the compiler then keeps them
+// in scalar registers for the span of one half-step only.
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int uniform_i32(int v) {
+  return __builtin_amdgcn_readfirstlane(v);
+}
 
-  float4 vec[C];
-  float4 acc[C];
+// D is the workgroup's LDS copy of the descriptor: its fields are re-read
+// where they are used (LDS is reloaded after every workgroup barrier), so
+// no more than one half-step's worth of them occupy scalar registers.
+template <class Dom>
+__device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl* ctl,
+                          uint64_t tlimit, float* lds, Shared& sh) {
+  const int g = uniform_i32(D.g);
+  const int r = uniform_i32(D.r);
+  BarrierState B{D.bar, &ctl->abort_flag, 0u, (unsigned)g, tlimit};
+  auto rlo = [&]() { return uniform_i64(D.n * br / g); };
+  auto rhi = [&]() { return uniform_i64(D.n * (br + 1) / g); };
+  auto clo = [&]() { return uniform_i64(D.m * br / g); };
+  auto chi = [&]() { return uniform_i64(D.m * (br + 1) / g); };
+  // ping-pong buffers: iteration k writes v^(k), w^(k) into buffer k & 1
+  auto vbuf = [&](int k) -> float* { return uniform_ptr((k & 1) ? D.v : D.v2); };
+  auto wbuf = [&](int k) -> float* { return uniform_ptr((k & 1) ? D.w : D.w2); };
+
+  typename Dom::State S;
   double err = 0.0;
   int bad = 0;
   bool ok = true;
   if (threadIdx.x == 0) D.members[br] = (int32_t)blockIdx.x;
 
   // z^(0) = Prow^T u^(0), u^(0) = 1 or the caller's start.
-  zero_acc(acc);
-  half_step<G, C, U, MODE_ACCUM>(D.Prow, rlo, rhi, r, vec,
-                                 D.warm ? D.u : nullptr, nullptr, nullptr,
-                                 acc, err, bad);
+  Dom::zero(S);
+  Dom::template half_step<MODE_ACCUM>(uniform_ptr(D.Prow), rlo(), rhi(), r,
+                                      uniform_i64(D.n), S, nullptr,
+                                      D.warm ? uniform_ptr(D.u) : nullptr,
+                                      nullptr, err, bad, lds);
   err = 0.0;
-  ok = finish_half_step<G, C>(D, br, B, acc, D.z, true, err, bad, lds_vec, sh);
+  ok = finish_half_step<Dom>(D, br, B, S, uniform_ptr(D.z), true, err, bad, lds, sh);
 
   int status = SK_OK;
   int kf = 0;
   double err_final = INFINITY;
   const bool fixed = D.fixed_iter > 0;
-  const int limit = fixed ? D.fixed_iter : D.max_iter;
-  if (ok && bad) { status = SK_ERANGE; }
+  const int limit = uniform_i32(fixed ? D.fixed_iter : D.max_iter);
+  if (ok && bad) status = SK_ERANGE;
 
   for (int k = 1; ok && status == SK_OK; ++k) {
     const bool last = k > limit;
-    load_vec<G, C>(D.z, r, vec);
-    zero_acc(acc);
+    Dom::load_vec(uniform_ptr(D.z), r, S, lds);
+    Dom::zero(S);
     err = 0.0;
     bad = 0;
     if (last) {
-      half_step<G, C, U, MODE_CHECK>(D.Pcol, clo, chi, r, vec, D.b,
-                                     vbuf[(k - 1) & 1], nullptr, acc, err, bad);
+      Dom::template half_step<MODE_CHECK>(uniform_ptr(D.Pcol), clo(), chi(), r,
+                                          uniform_i64(D.m), S, uniform_ptr(D.b),
+                                          vbuf(k - 1), nullptr, err, bad,
+                                          lds);
     } else if (k >= 2) {
-      half_step<G, C, U, MODE_UPDATE_CHECK>(D.Pcol, clo, chi, r, vec, D.b,
-                                            vbuf[(k - 1) & 1], vbuf[k & 1],
-                                            acc, err, bad);
+      Dom::template half_step<MODE_UPDATE_CHECK>(uniform_ptr(D.Pcol), clo(), chi(),
+                                                 r, uniform_i64(D.m), S,
+                                                 uniform_ptr(D.b), vbuf(k - 1),
+                                                 vbuf(k), err, bad, lds);
     } else {
-      half_step<G, C, U, MODE_UPDATE>(D.Pcol, clo, chi, r, vec, D.b, nullptr,
-                                      vbuf[k & 1], acc, err, bad);
+      Dom::template half_step<MODE_UPDATE>(uniform_ptr(D.Pcol), clo(), chi(), r,
+                                           uniform_i64(D.m), S, uniform_ptr(D.b),
+                                           nullptr, vbuf(k), err, bad, lds);
     }
-    ok = finish_half_step<G, C>(D, br, B, acc, wbuf[k & 1], !last, err, bad,
-                                lds_vec, sh);
+    ok = finish_half_step<Dom>(D, br, B, S, wbuf(k), !last, err, bad, lds, sh);
     if (!ok) break;
     if (k >= 2) err_final = err;  // error of iteration k-1
     if (bad) {
@@ -424,13 +932,14 @@ __device__ void run_solve(const SolveDesc& D, int br, LaunchCtl* ctl,
       break;
     }
     // u-half-step with w^(k).
-    load_vec<G, C>(wbuf[k & 1], r, vec);
-    zero_acc(acc);
+    Dom::load_vec(wbuf(k), r, S, lds);
+    Dom::zero(S);
     err = 0.0;
     bad = 0;
-    half_step<G, C, U, MODE_UPDATE>(D.Prow, rlo, rhi, r, vec, D.a, nullptr,
-                                    D.u, acc, err, bad);
-    ok = finish_half_step<G, C>(D, br, B, acc, D.z, true, err, bad, lds_vec, sh);
+    Dom::template half_step<MODE_UPDATE>(uniform_ptr(D.Prow), rlo(), rhi(), r,
+                                         uniform_i64(D.n), S, uniform_ptr(D.a),
+                                         nullptr, uniform_ptr(D.u), err, bad, lds);
+    ok = finish_half_step<Dom>(D, br, B, S, uniform_ptr(D.z), true, err, bad, lds, sh);
     if (!ok) break;
     if (bad) {
       status = SK_ERANGE;
@@ -450,23 +959,23 @@ __device__ void run_solve(const SolveDesc& D, int br, LaunchCtl* ctl,
   }
 
   // Final pair: u^(kf) in D.u, v^(kf) in vbuf[kf&1], w^(kf) in wbuf[kf&1].
-  const float* vfin = vbuf[kf & 1];
+  const float* vfin = vbuf(kf);
   double part = 0.0;
   if (kf >= 1) {
-    const bool copy = vfin != D.v;
-    for (int64_t j = clo + threadIdx.x; j < chi; j += kBlock) {
-      const float vj = vfin[j];
-      if (copy) D.v[j] = vj;
-      double lv = log((double)vj);
+    const bool copy = (kf & 1) == 0;
+    const int64_t c0 = clo(), c1 = chi(), r0 = rlo(), r1 = rhi();
+    for (int64_t j = c0 + threadIdx.x; j < c1; j += kBlock) {
+      if (copy) Dom::copy_scaling(vfin, D.v, j, D.m);
+      double lv = Dom::log_scaling(vfin, j, D.m);
       if (D.scol) lv -= (double)D.scol[j];
       part += (double)D.b[j] * lv;
     }
     if (copy && br == 0) {
-      const float* wfin = wbuf[kf & 1];
-      for (int c = threadIdx.x; c < r; c += kBlock) D.w[c] = wfin[c];
+      const float* wfin = wbuf(kf);
+      for (int c = threadIdx.x; c < r * Dom::kVecStride; c += kBlock) D.w[c] = wfin[c];
     }
-    for (int64_t i = rlo + threadIdx.x; i < rhi; i += kBlock) {
-      double lu = log((double)D.u[i]);
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
+      double lu = Dom::log_scaling(D.u, i, D.n);
       if (D.srow) lu -= (double)D.srow[i];
       part += (double)D.a[i] * lu;
     }
@@ -488,13 +997,16 @@ __device__ void run_solve(const SolveDesc& D, int br, LaunchCtl* ctl,
   }
 }
 
-template <int G, int C, int U>
+template <class Dom>
 __global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(Dom::kWavesPerEU, 8)))
 solver_kernel(const SolveDesc* __restrict__ descs, int count, int total_seats,
               LaunchCtl* ctl, uint64_t tlimit) {
-  __shared__ float4 lds_vec[(kWaves * G * C) > kBlock ? (kWaves * G * C) : kBlock];
+  __shared__ float4 lds4[Dom::kLdsFloats / 4];
   __shared__ Shared sh;
   __shared__ int s_seat;
+  __shared__ SolveDesc sD;
+  float* lds = reinterpret_cast<float*>(lds4);
   for (;;) {
     if (threadIdx.x == 0) {
       int seat = -1;
@@ -504,7 +1016,9 @@ solver_kernel(const SolveDesc* __restrict__ descs, int count, int total_seats,
       s_seat = seat;
     }
     __syncthreads();
-    const int seat = s_seat;
+    // the seat is uniform across the workgroup: keep it (and everything
+    // derived from it, the descriptor included) in scalar registers
+    const int seat = __builtin_amdgcn_readfirstlane(s_seat);
     __syncthreads();
     if (seat < 0 || seat >= total_seats) return;
     // find the solve owning this seat (descs sorted by seat0)
@@ -513,8 +1027,16 @@ solver_kernel(const SolveDesc* __restrict__ descs, int count, int total_seats,
       const int mid = (lo + hi + 1) >> 1;
       if (descs[mid].seat0 <= seat) lo = mid; else hi = mid - 1;
     }
-    const SolveDesc D = descs[lo];
-    run_solve<G, C, U>(D, seat - D.seat0, ctl, tlimit, lds_vec, sh);
+    {
+      static_assert(sizeof(SolveDesc) % 4 == 0, "descriptor copy granularity");
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(descs + lo);
+      uint32_t* dst = reinterpret_cast<uint32_t*>(&sD);
+      for (int i = threadIdx.x; i < (int)(sizeof(SolveDesc) / 4); i += kBlock)
+        dst[i] = src[i];
+    }
+    __syncthreads();
+    const int br = seat - uniform_i32(sD.seat0);
+    run_solve<Dom>(sD, br, ctl, tlimit, lds, sh);
     __syncthreads();
   }
 }
@@ -538,31 +1060,32 @@ __global__ void upload_kernel(unsigned char* dst, UploadPayload p, int nbytes) {
 }
 
 // ----------------------------------------------------------- dispatch table
-typedef void (*SolverFn)(const SolveDesc*, int, int, LaunchCtl*, uint64_t);
-
 struct SolverClass {
   int rmax;             // largest r of the class
-  const void* fn;       // kernel symbol
-  void (*launch)(dim3, hipStream_t, const SolveDesc*, int, int, LaunchCtl*,
-                 uint64_t);
+  const void* fn[2];    // kernel symbols: linear, extended range
+  void (*launch[2])(dim3, hipStream_t, const SolveDesc*, int, int, LaunchCtl*,
+                    uint64_t);
 };
 
-template <int G, int C, int U>
+template <class Dom>
 void launch_cls(dim3 grid, hipStream_t s, const SolveDesc* d, int count,
                 int seats, LaunchCtl* ctl, uint64_t tl) {
-  hipLaunchKernelGGL((solver_kernel<G, C, U>), grid, dim3(kBlock), 0, s, d,
-                     count, seats, ctl, tl);
+  hipLaunchKernelGGL((solver_kernel<Dom>), grid, dim3(kBlock), 0, s, d, count,
+                     seats, ctl, tl);
 }
 
-#define SK_CLASS(G, C, U) \
-  { 4 * (G) * (C), reinterpret_cast<const void*>(&solver_kernel<G, C, U>), &launch_cls<G, C, U> }
+#define SK_CLASS(G, C, U, UX)                                                \
+  {4 * (G) * (C),                                                            \
+   {reinterpret_cast<const void*>(&solver_kernel<LinearDomain<G, C, U>>),    \
+    reinterpret_cast<const void*>(&solver_kernel<XRangeDomain<G, C, UX>>)},  \
+   {&launch_cls<LinearDomain<G, C, U>>, &launch_cls<XRangeDomain<G, C, UX>>}}
 
 const SolverClass kClasses[] = {
-    SK_CLASS(1, 1, 4),   SK_CLASS(2, 1, 4),   SK_CLASS(4, 1, 4),
-    SK_CLASS(8, 1, 4),   SK_CLASS(16, 1, 4),  SK_CLASS(32, 1, 4),
-    SK_CLASS(64, 1, 4),  SK_CLASS(64, 2, 4),  SK_CLASS(64, 3, 2),
-    SK_CLASS(64, 4, 2),  SK_CLASS(64, 6, 2),  SK_CLASS(64, 8, 1),
-    SK_CLASS(64, 12, 1), SK_CLASS(64, 16, 1),
+    SK_CLASS(1, 1, 2, 2),   SK_CLASS(2, 1, 2, 2),   SK_CLASS(4, 1, 2, 2),
+    SK_CLASS(8, 1, 2, 2),   SK_CLASS(16, 1, 2, 2),  SK_CLASS(32, 1, 2, 2),
+    SK_CLASS(64, 1, 2, 2),  SK_CLASS(64, 2, 2, 1),  SK_CLASS(64, 3, 1, 1),
+    SK_CLASS(64, 4, 1, 1),  SK_CLASS(64, 6, 1, 1),  SK_CLASS(64, 8, 1, 1),
+    SK_CLASS(64, 12, 1, 1), SK_CLASS(64, 16, 1, 1),
 };
 constexpr int kNumClasses = sizeof(kClasses) / sizeof(kClasses[0]);
 
@@ -592,7 +1115,7 @@ int solver_class_rmax(int r) {
   return cls ? cls->rmax : 0;
 }
 
-int solver_capacity(int r) {
+int solver_capacity(int r, int xr) {
   const SolverClass* cls = class_for(r);
   if (!cls) return 0;
   int dev = 0;
@@ -602,23 +1125,11 @@ int solver_capacity(int r) {
       hipSuccess)
     return 0;
   int per = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, cls->fn, kBlock, 0) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, cls->fn[xr ? 1 : 0],
+                                                   kBlock, 0) != hipSuccess)
     return 0;
   if (per < 1) per = 1;
   return per * cus;
-}
-
-int solver_group_size(int64_t n, int64_t m, int r, int capacity) {
-  // Aim at a few thousand feature bytes... per workgroup per half-step:
-  // small problems use few workgroups (barriers are not free), large ones
-  // spread over the whole device.
-  const int64_t rows = n > m ? n : m;
-  const int64_t bytes = rows * (int64_t)r * 4;
-  int64_t g = bytes / (256 * 1024);  // ~256 KB of features per workgroup
-  if (g < 1) g = 1;
-  if (g > capacity) g = capacity;
-  return (int)g;
 }
 
 hipError_t upload_bytes(void* dev, const void* host, size_t total,
@@ -652,14 +1163,17 @@ hipError_t launch_init_ctl(LaunchCtl* ctl, unsigned* bars, int nbars,
   return hipGetLastError();
 }
 
-hipError_t launch_solver(const SolveDesc* dev_descs, int count, int r,
+hipError_t launch_solver(const SolveDesc* dev_descs, int count, int r, int xr,
                          int total_seats, int grid, LaunchCtl* ctl,
                          hipStream_t s) {
   const SolverClass* cls = class_for(r);
   if (!cls) return hipErrorInvalidValue;
-  cls->launch(dim3(grid), s, dev_descs, count, total_seats, ctl,
-              timeout_ticks());
-  return hipGetLastError();
+  void* tok = prof_begin(kProfSolver, s);
+  cls->launch[xr ? 1 : 0](dim3(grid), s, dev_descs, count, total_seats, ctl,
+                          timeout_ticks());
+  const hipError_t e = hipGetLastError();
+  prof_end(tok, s);
+  return e;
 }
 
 }  // namespace sk

@@ -75,11 +75,12 @@ def test_argument_errors_return_before_any_device_work(L):
     P = ctypes.c_void_p(0x1000)
     o = _lib.sk_solve_opts(1e-6, 100, 0, 0, 0)
     # features
-    assert L.sinkhorn_features(None, 10, 2, P, 8, 0.5, 2.0, P, P, None) == _lib.SK_EINVAL
-    assert L.sinkhorn_features(P, 0, 2, P, 8, 0.5, 2.0, P, P, None) == _lib.SK_EINVAL
-    assert L.sinkhorn_features(P, 10, 2, P, 8, 0.0, 2.0, P, P, None) == _lib.SK_EINVAL
-    assert L.sinkhorn_features(P, 10, 2, P, 8, 0.5, 0.4, P, P, None) == _lib.SK_EINVAL
-    assert L.sinkhorn_features(P, 10, 2, P, 5000, 0.5, 2.0, P, P, None) == _lib.SK_ENOTSUP
+    assert L.sinkhorn_features(None, 10, 2, P, 8, 0.5, 2.0, 0, P, P, None) == _lib.SK_EINVAL
+    assert L.sinkhorn_features(P, 0, 2, P, 8, 0.5, 2.0, 0, P, P, None) == _lib.SK_EINVAL
+    assert L.sinkhorn_features(P, 10, 2, P, 8, 0.0, 2.0, 0, P, P, None) == _lib.SK_EINVAL
+    assert L.sinkhorn_features(P, 10, 2, P, 8, 0.5, 0.4, 1, P, P, None) == _lib.SK_EINVAL
+    assert L.sinkhorn_features(P, 10, 2, P, 8, 0.5, 2.0, 2, P, P, None) == _lib.SK_EINVAL
+    assert L.sinkhorn_features(P, 10, 2, P, 5000, 0.5, 2.0, 0, P, P, None) == _lib.SK_ENOTSUP
     # solve
     args = [P, 10, P, 12, 8, P, P, ctypes.byref(o), P, P, P, P, P, P, 1 << 20, None]
     bad = list(args); bad[0] = None
@@ -93,6 +94,9 @@ def test_argument_errors_return_before_any_device_work(L):
     assert L.sinkhorn_solve(*bad) == _lib.SK_EINVAL
     o3 = _lib.sk_solve_opts(1e-6, 0, 0, 0, 0)
     bad = list(args); bad[7] = ctypes.byref(o3)
+    assert L.sinkhorn_solve(*bad) == _lib.SK_EINVAL
+    o4 = _lib.sk_solve_opts(1e-6, 10, 0, 0, 7)   # unknown numeric domain
+    bad = list(args); bad[7] = ctypes.byref(o4)
     assert L.sinkhorn_solve(*bad) == _lib.SK_EINVAL
     bad = list(args); bad[14] = 16   # workspace too small
     assert L.sinkhorn_solve(*bad) == _lib.SK_ENOMEM
@@ -120,8 +124,10 @@ def test_argument_errors_return_before_any_device_work(L):
     # backward
     assert L.sinkhorn_divergence_backward(ctypes.byref(p), None, None, P, P, P, P,
                                           P, 1 << 20, None) == _lib.SK_EINVAL
-    assert L.sinkhorn_features_backward(P, 10, 2, P, 6, P, P, P, 1.0, 0, P,
+    assert L.sinkhorn_features_backward(P, 10, 2, P, 6, P, P, P, 1.0, 0, 0, P,
                                         None) == _lib.SK_ENOTSUP
+    assert L.sinkhorn_features_backward(P, 10, 2, P, 8, P, P, P, 1.0, 0, 5, P,
+                                        None) == _lib.SK_EINVAL
 
 
 def test_state_layout_is_aligned_and_disjoint(L):
@@ -129,11 +135,11 @@ def test_state_layout_is_aligned_and_disjoint(L):
     lay = _lib.sk_state_layout()
     assert L.sinkhorn_state_layout(n, m, r, ctypes.byref(lay)) == _lib.SK_OK
     pieces = [(lay.phix, 4 * n * r), (lay.phiy, 4 * m * r), (lay.sx, 4 * n),
-              (lay.sy, 4 * m), (lay.info, 72), (lay.out, 32)]
+              (lay.sy, 4 * m), (lay.info, 72), (lay.out, 32), (lay.meta, 16)]
     rows_u, rows_v = (n, n, m), (m, n, m)
-    for k in range(3):
-        pieces += [(lay.u[k], 4 * rows_u[k]), (lay.v[k], 4 * rows_v[k]),
-                   (lay.w[k], 4 * r), (lay.z[k], 4 * r)]
+    for k in range(3):   # pair layout [E | M]: 8 bytes per entry
+        pieces += [(lay.u[k], 8 * rows_u[k]), (lay.v[k], 8 * rows_v[k]),
+                   (lay.w[k], 8 * r), (lay.z[k], 8 * r)]
     pieces.sort()
     for (o1, s1), (o2, _) in zip(pieces, pieces[1:]):
         assert o1 % 256 == 0 and o1 + s1 <= o2

@@ -3,7 +3,8 @@ oracle on the same seeded float32 inputs.
 
 Tolerances: divergences within 1e-5 relative, gradients within 1e-4
 relative (L2), features within a bound derived from float32 rounding of
-the exponent (see _feature_tol).
+the exponent (see _feature_tol).  Both numeric domains of the solver are
+exercised: the extended range (default) and plain float32 (LINEAR).
 """
 import math
 import sys
@@ -19,6 +20,9 @@ pytestmark = pytest.mark.gpu
 
 DIV_RTOL = 1e-5
 GRAD_RTOL = 1e-4
+EXT, LIN = 0, 1
+RANGES = [pytest.param(EXT, id="ext"), pytest.param(LIN, id="lin")]
+LOG2E = 1.0 / math.log(2.0)
 
 
 def _say(*a):
@@ -58,6 +62,7 @@ def _feature_tol(X, U, eps, q):
     return 8 * 2.0 ** -24 * (mag.max(1) + 1.0)
 
 
+@pytest.mark.parametrize("rng_mode", RANGES)
 @pytest.mark.parametrize("n,d,r,eps,q", [
     (1000, 2, 128, 0.5, 8.0),        # the small 2-D workload
     (1037, 3, 1024, 0.1, 9.17),      # mixture-like shape, ragged n
@@ -68,57 +73,72 @@ def _feature_tol(X, U, eps, q):
     (150, 128, 2048, 1.0, 0.504),    # d = 128, anchors read from memory
     (64, 2, 4096, 0.5, 8.0),         # largest r
 ])
-def test_features_match_oracle(api, n, d, r, eps, q):
-    _say("features", n, d, r, eps)
+def test_features_match_oracle(api, n, d, r, eps, q, rng_mode):
+    _say("features", n, d, r, eps, rng_mode)
     rng = np.random.default_rng(n + d + r)
     X = rng.standard_normal((n, d)).astype(np.float32)
     U = (math.sqrt(oracle.sigma2_from_q(q, eps)) *
          rng.standard_normal((r, d))).astype(np.float32)
-    Phi, s = api.features(dev(X), dev(U), eps, q)
+    Phi, s = api.features(dev(X), dev(U), eps, q, range=rng_mode)
     torch.cuda.synchronize()
     Pg, sg = host(Phi), host(s)
-    Po, so = oracle.gaussian_features_scaled(X, U, eps, q)
+    E = oracle.gaussian_log_features(X, U, eps, q)
+    so = E.max(1)
     tol = _feature_tol(X, U, eps, q)
     assert np.all(np.abs(sg - so) <= tol), np.max(np.abs(sg - so) / tol)
-    big = Po > 1e-30
-    rel = np.abs(Pg - Po) / np.where(big, Po, 1.0)
-    assert np.all(rel[big] <= 2 * np.broadcast_to(tol[:, None], Po.shape)[big] + 4e-7)
-    assert np.all(np.abs(Pg - Po)[~big] <= 1e-30)
-    assert np.all(Pg <= 1.0) and np.all(Pg >= 0.0)
+    if rng_mode == EXT:
+        Lo = (E - so[:, None]) * LOG2E
+        err = np.abs(Pg - Lo)
+        assert np.all(err <= 2 * LOG2E * tol[:, None] + 4e-7 * np.abs(Lo)), err.max()
+        assert np.all(Pg <= 0.0)
+    else:
+        Po = np.exp(E - so[:, None])
+        big = Po > 1e-30
+        rel = np.abs(Pg - Po) / np.where(big, Po, 1.0)
+        assert np.all(rel[big] <= 2 * np.broadcast_to(tol[:, None], Po.shape)[big] + 4e-7)
+        assert np.all(np.abs(Pg - Po)[~big] <= 1e-30)
+        assert np.all(Pg <= 1.0) and np.all(Pg >= 0.0)
 
 
-def _solve_case(api, n, m, r, iters, seed):
-    rng = np.random.default_rng(seed)
-    X = rng.standard_normal((n, 2))
-    Y = rng.standard_normal((m, 2)) + 1.0
-    U = rng.standard_normal((r, 2))
-    Px, _ = oracle.gaussian_features_scaled(X, U, 0.5, 8.0)
-    Py, _ = oracle.gaussian_features_scaled(Y, U, 0.5, 8.0)
-    Px = Px.astype(np.float32)
-    Py = Py.astype(np.float32)
-    a = inputs.dirichlet_weights(rng, n)
-    b = inputs.dirichlet_weights(rng, m)
-    res = api.solve(dev(Px), dev(Py), dev(a), dev(b), fixed_iter=iters)
-    info = res.info()
-    ref = oracle.sinkhorn_factored(Px, Py, a, b, fixed_iter=iters)
-    return res, info, ref, (Px, Py, a, b)
-
-
+@pytest.mark.parametrize("rng_mode", RANGES)
 @pytest.mark.parametrize("n,m,r,iters", [(1000, 1000, 128, 50), (777, 1203, 64, 30),
                                          (5000, 3000, 256, 20), (40000, 30000, 512, 10),
                                          (3, 2, 4, 5)])
-def test_solve_matches_oracle_fixed_iterations(api, n, m, r, iters):
+def test_solve_matches_oracle_fixed_iterations(api, n, m, r, iters, rng_mode):
     """Algorithm 1 from u = 1 for a fixed number of iterations on features
-    produced by the oracle (rounded to float32): scalings, r-vectors, the
-    reported iteration count and error."""
-    _say("solve", n, m, r, iters)
-    res, info, ref, (Px, Py, a, b) = _solve_case(api, n, m, r, iters, n + m)
+    produced by the oracle (rounded to float32; log2 features for the
+    extended range): scalings, r-vectors, iteration count and error."""
+    _say("solve", n, m, r, iters, rng_mode)
+    rng = np.random.default_rng(n + m)
+    X = rng.standard_normal((n, 2))
+    Y = rng.standard_normal((m, 2)) + 1.0
+    U = rng.standard_normal((r, 2))
+    Ex = oracle.gaussian_log_features(X, U, 0.5, 8.0)
+    Ey = oracle.gaussian_log_features(Y, U, 0.5, 8.0)
+    Lx = Ex - Ex.max(1)[:, None]
+    Ly = Ey - Ey.max(1)[:, None]
+    if rng_mode == EXT:
+        Gx, Gy = (Lx * LOG2E).astype(np.float32), (Ly * LOG2E).astype(np.float32)
+        Px = np.exp2(Gx.astype(np.float64))
+        Py = np.exp2(Gy.astype(np.float64))
+    else:
+        Gx, Gy = np.exp(Lx).astype(np.float32), np.exp(Ly).astype(np.float32)
+        Px, Py = Gx.astype(np.float64), Gy.astype(np.float64)
+    a = inputs.dirichlet_weights(rng, n)
+    b = inputs.dirichlet_weights(rng, m)
+    res = api.solve(dev(Gx), dev(Gy), dev(a), dev(b), fixed_iter=iters,
+                    range=rng_mode)
+    info = res.info()
+    ref = oracle.sinkhorn_factored(Px, Py, a, b, fixed_iter=iters)
     assert info["status"] == 0 and info["iters"] == iters
-    u, v = host(res.u), host(res.v)
-    np.testing.assert_allclose(u, ref.u, rtol=2e-4)
-    np.testing.assert_allclose(v, ref.v, rtol=2e-4)
-    np.testing.assert_allclose(host(res.w), Py.astype(np.float64).T @ ref.v, rtol=2e-4)
-    np.testing.assert_allclose(host(res.z), Px.astype(np.float64).T @ ref.u, rtol=2e-4)
+    lu = api.host_log_scaling(res.u, rng_mode)
+    lv = api.host_log_scaling(res.v, rng_mode)
+    np.testing.assert_allclose(lu, np.log(ref.u), rtol=0, atol=2e-4)
+    np.testing.assert_allclose(lv, np.log(ref.v), rtol=0, atol=2e-4)
+    lw = api.host_log_scaling(res.w, rng_mode)
+    lz = api.host_log_scaling(res.z, rng_mode)
+    np.testing.assert_allclose(lw, np.log(Py.T @ ref.v), rtol=0, atol=2e-4)
+    np.testing.assert_allclose(lz, np.log(Px.T @ ref.u), rtol=0, atol=2e-4)
     wo = oracle.w_hat(ref.u, ref.v, a, b, 1.0)
     assert info["w_hat"] == pytest.approx(wo, rel=DIV_RTOL, abs=1e-7)
     assert info["err"] == pytest.approx(ref.err, rel=0.05, abs=2e-6)
@@ -140,13 +160,14 @@ def _divergence_inputs(kind, seed=0, **kw):
     return c, U, eps, q
 
 
-def test_divergence_small_gaussians_200_iterations(api):
+@pytest.mark.parametrize("rng_mode", RANGES)
+def test_divergence_small_gaussians_200_iterations(api, rng_mode):
     """The 2-D Gaussian workload: n = m = 1000, r = 128, sigma^2 = 1,
     200 fixed iterations; GPU float32 vs oracle float64 (dense K_theta)."""
-    _say("divergence gauss2d 200 fixed")
+    _say("divergence gauss2d 200 fixed", rng_mode)
     c, U, eps, q = _divergence_inputs("gauss2d")
     out, st = api.divergence(dev(c.X), dev(c.Y), dev(c.a), dev(c.b), dev(U),
-                             eps, q, fixed_iter=200)
+                             eps, q, fixed_iter=200, range=rng_mode)
     g = host(out)
     ref = oracle.divergence(c.X, c.Y, c.a, c.b, U, eps, q, fixed_iter=200)
     _say("W_bar gpu", g[0], "oracle", ref.value)
@@ -158,15 +179,16 @@ def test_divergence_small_gaussians_200_iterations(api):
     assert list(infos["status"]) == [0, 0, 0]
 
 
-def test_divergence_tolerance_mode(api):
+@pytest.mark.parametrize("rng_mode", RANGES)
+def test_divergence_tolerance_mode(api, rng_mode):
     """Stop test of Algorithm 1 at tol = 1e-6: both sides converge and agree
     within 1e-5; the reported error is below the tolerance and the
     iteration counts agree to a few iterations (float32 vs float64 may
     cross the threshold at slightly different iterations)."""
-    _say("divergence gauss2d tol")
+    _say("divergence gauss2d tol", rng_mode)
     c, U, eps, q = _divergence_inputs("gauss2d")
     out, st = api.divergence(dev(c.X), dev(c.Y), dev(c.a), dev(c.b), dev(U),
-                             eps, q, tol=1e-6, max_iter=5000)
+                             eps, q, tol=1e-6, max_iter=5000, range=rng_mode)
     g = host(out)
     ref = oracle.divergence(c.X, c.Y, c.a, c.b, U, eps, q, tol=1e-6, max_iter=5000)
     infos = st.infos()
@@ -177,14 +199,119 @@ def test_divergence_tolerance_mode(api):
     assert g[0] == pytest.approx(ref.value, rel=DIV_RTOL)
 
 
+def test_separated_mixtures_extended_range_converges(api):
+    """Two 4-component mixtures in R^3 at eps = 0.1 (clusters far apart, the
+    mixture workload at n = m = 3000): the extended range converges to the
+    float64 oracle's divergence within 1e-5 at tol = 1e-6."""
+    _say("separated mixtures")
+    c, U, eps, q = _divergence_inputs("gmm3d", seed=0, n=3000, m=3000)
+    args = (dev(c.X), dev(c.Y), dev(c.a), dev(c.b), dev(U), eps, q)
+    out, st = api.divergence(*args, tol=1e-6, max_iter=3000, range=EXT)
+    infos = st.infos()
+    assert list(infos["status"]) == [0, 0, 0], infos
+    ref = oracle.divergence_scaled(c.X, c.Y, c.a, c.b, U, eps, q, tol=1e-6,
+                                   max_iter=3000, dense=False)
+    g = host(out)
+    _say("W_bar gpu", g[0], "oracle", ref.value, "iters", infos["iters"],
+         ref.xy.iters, ref.xx.iters, ref.yy.iters)
+    assert g[0] == pytest.approx(ref.value, rel=DIV_RTOL)
+
+
+def _marginal_checks(c, U, eps, q, st, rows, tol):
+    """Properties of the converged (x, y) solve that hold at any size,
+    checked in float64 on the host with features recomputed by the oracle
+    (independently of the GPU's features) on sampled points:
+      * row marginal (exact after the u-update of Algorithm 1):
+        u_i sum_k phi_k(x_i) w_k = a_i,
+      * column marginal of the returned pair within the stop tolerance:
+        v_j sum_k phi_k(y_j) z_k ~ b_j,
+    with (u, v, w, z) the GPU's scalings and r-vectors.  The tolerance
+    covers float32 feature rounding of exponents of a few hundred."""
+    lu, lv = st.log_scalings(0)
+    _, _, w, z = st.scalings(0)
+    lw = api_host_log(w, st.range)
+    lz = api_host_log(z, st.range)
+    rng = np.random.default_rng(7)
+    ii = rng.choice(len(c.a), size=min(rows, len(c.a)), replace=False)
+    jj = rng.choice(len(c.b), size=min(rows, len(c.b)), replace=False)
+    sx = st.sx.cpu().numpy().astype(np.float64)
+    sy = st.sy.cpu().numpy().astype(np.float64)
+    Ex = oracle.gaussian_log_features(c.X[ii], U, eps, q)
+    Ey = oracle.gaussian_log_features(c.Y[jj], U, eps, q)
+    # log of u_i phi_k(x_i) w_k with the GPU's scaled u (u = u~ e^{-s})
+    row = np.exp(lu[ii, None] - sx[ii, None] + Ex + lw[None, :]).sum(1)
+    np.testing.assert_allclose(row, c.a[ii].astype(np.float64), rtol=1e-3)
+    col = np.exp(lv[jj, None] - sy[jj, None] + Ey + lz[None, :]).sum(1)
+    np.testing.assert_allclose(col, c.b[jj].astype(np.float64), rtol=1e-3)
+
+
+def api_host_log(t, range_):
+    from paper_2006_07057_amd import api as A
+    return A.host_log_scaling(t, range_)
+
+
+def test_linear_overflow_detected_extended_converges(api):
+    """Mixture workload at n = m = 20000: the float32 scalings of the
+    (x, y) problem overflow, which the linear domain reports as SK_ERANGE
+    (no silent NaN); the extended range converges and its solution passes
+    float64 marginal checks on sampled points."""
+    _say("linear overflow vs extended range")
+    c, U, eps, q = _divergence_inputs("gmm3d", seed=0, n=20000, m=20000)
+    args = (dev(c.X), dev(c.Y), dev(c.a), dev(c.b), dev(U), eps, q)
+    _, st_lin = api.divergence(*args, tol=1e-6, max_iter=3000, range=LIN)
+    assert st_lin.infos()["status"][0] == 3
+    out, st = api.divergence(*args, tol=1e-6, max_iter=3000, range=EXT)
+    infos = st.infos()
+    assert list(infos["status"]) == [0, 0, 0], infos
+    assert np.all(infos["err"] < 1e-6)
+    _marginal_checks(c, U, eps, q, st, 500, 1e-6)
+
+
+def test_full_size_mixture_properties(api):
+    """The benchmark configuration itself (n = m = 10^6 points in R^3,
+    r = 1024, eps = 0.1, tol 1e-6, at most 2000 iterations, extended range,
+    the same entry point and launch as the benchmark): every solve ends
+    with status OK or SK_ENOTCONV, the reported error of converged solves
+    is below the tolerance, the divergence is the float64 combination of
+    the three dual estimates, features of sampled rows match the oracle,
+    and the (x, y) solution passes float64 marginal checks on sampled
+    points."""
+    _say("full-size mixture workload")
+    c, U, eps, q = _divergence_inputs("gmm3d", seed=0)
+    args = (dev(c.X), dev(c.Y), dev(c.a), dev(c.b), dev(U), eps, q)
+    out, st = api.divergence(*args, tol=1e-6, max_iter=2000, range=EXT)
+    infos = st.infos()
+    g = host(out)
+    _say("infos", infos, "W_bar", g[0])
+    assert set(int(s) for s in infos["status"]) <= {0, 4}
+    for k in range(3):
+        if infos["status"][k] == 0:
+            assert infos["err"][k] < 1e-6
+    assert g[0] == pytest.approx(g[1] - 0.5 * (g[2] + g[3]), rel=1e-12)
+    # features of sampled rows against the oracle
+    rng = np.random.default_rng(3)
+    ii = rng.choice(len(c.a), size=256, replace=False)
+    E = oracle.gaussian_log_features(c.X[ii], U, eps, q)
+    so = E.max(1)
+    sg = st.sx.cpu().numpy().astype(np.float64)[ii]
+    tol = _feature_tol(c.X[ii], U, eps, q)
+    assert np.all(np.abs(sg - so) <= tol)
+    Lg = st.phix[torch.from_numpy(ii).cuda()].cpu().numpy().astype(np.float64)
+    Lo = (E - so[:, None]) * LOG2E
+    assert np.all(np.abs(Lg - Lo) <= 2 * LOG2E * tol[:, None] + 4e-7 * np.abs(Lo))
+    if infos["status"][0] == 0:
+        _marginal_checks(c, U, eps, q, st, 300, 1e-6)
+
+
+@pytest.mark.parametrize("rng_mode", RANGES)
 @pytest.mark.parametrize("n,m,d,r,eps", [
     (1037, 555, 3, 100, 0.5), (90, 140, 1, 4, 1.0), (2000, 1500, 16, 512, 2.0),
     (513, 511, 2, 1024, 0.3), (300, 200, 5, 2048, 1.0), (120, 130, 2, 4096, 0.5),
     (64, 64, 2, 12, 0.5), (1, 1, 2, 8, 1.0),
 ])
-def test_divergence_shapes(api, n, m, d, r, eps):
+def test_divergence_shapes(api, n, m, d, r, eps, rng_mode):
     """Ragged sizes across every solver class (30 fixed iterations)."""
-    _say("divergence shapes", n, m, d, r, eps)
+    _say("divergence shapes", n, m, d, r, eps, rng_mode)
     rng = np.random.default_rng(n * 7 + m)
     X = rng.standard_normal((n, d)).astype(np.float32)
     Y = (rng.standard_normal((m, d)) + 0.5).astype(np.float32)
@@ -193,7 +320,7 @@ def test_divergence_shapes(api, n, m, d, r, eps):
     q = oracle.lambert_q(inputs.max_norm(X, Y), eps, d)
     U = inputs.gaussian_anchors(n + m, r, d, oracle.sigma2_from_q(q, eps))
     out, st = api.divergence(dev(X), dev(Y), dev(a), dev(b), dev(U), eps, q,
-                             fixed_iter=30)
+                             fixed_iter=30, range=rng_mode)
     g = host(out)
     ref = oracle.divergence_scaled(X, Y, a, b, U, eps, q, fixed_iter=30)
     scale = max(abs(ref.value), 1e-3 * max(abs(ref.w_xy), 1.0))
@@ -202,14 +329,15 @@ def test_divergence_shapes(api, n, m, d, r, eps):
         assert g[1 + k] == pytest.approx(w, rel=DIV_RTOL, abs=1e-6)
 
 
-def test_divergence_multi_workgroup_groups(api):
+@pytest.mark.parametrize("rng_mode", RANGES)
+def test_divergence_multi_workgroup_groups(api, rng_mode):
     """Large enough that every solve spans many workgroups (group barriers
     and the cross-workgroup reduction are exercised), compared with the
     factored oracle at fixed iterations."""
-    _say("divergence multi-workgroup")
+    _say("divergence multi-workgroup", rng_mode)
     c, U, eps, q = _divergence_inputs("gmm3d", seed=3, n=60000, m=50000)
     out, st = api.divergence(dev(c.X), dev(c.Y), dev(c.a), dev(c.b), dev(U),
-                             eps, q, fixed_iter=8)
+                             eps, q, fixed_iter=8, range=rng_mode)
     g = host(out)
     ref = oracle.divergence_scaled(c.X, c.Y, c.a, c.b, U, eps, q, fixed_iter=8,
                                    dense=False)
@@ -217,11 +345,12 @@ def test_divergence_multi_workgroup_groups(api):
     assert g[0] == pytest.approx(ref.value, rel=DIV_RTOL)
 
 
-def test_batched_equals_single(api):
+@pytest.mark.parametrize("rng_mode", RANGES)
+def test_batched_equals_single(api, rng_mode):
     """Several uneven problems in one batched call give the same results as
     each problem alone (each solve's arithmetic does not depend on what
     else shares the launch)."""
-    _say("batched vs single")
+    _say("batched vs single", rng_mode)
     probs = []
     rng = np.random.default_rng(5)
     for (n, m, d, r, eps) in [(1000, 800, 2, 128, 0.5), (5000, 7000, 3, 256, 0.2),
@@ -234,19 +363,21 @@ def test_batched_equals_single(api):
         q = oracle.lambert_q(inputs.max_norm(X, Y), eps, d)
         U = inputs.gaussian_anchors(n, r, d, oracle.sigma2_from_q(q, eps))
         probs.append((dev(X), dev(Y), dev(a), dev(b), dev(U), eps, q))
-    outb, sts = api.divergence_batched(probs, tol=1e-6, max_iter=3000)
+    outb, sts = api.divergence_batched(probs, tol=1e-6, max_iter=3000,
+                                       range=rng_mode)
     ob = host(outb)
     for i, P in enumerate(probs):
-        o1, s1 = api.divergence(*P, tol=1e-6, max_iter=3000)
+        o1, s1 = api.divergence(*P, tol=1e-6, max_iter=3000, range=rng_mode)
         o1 = host(o1)
         np.testing.assert_array_equal(ob[i], o1)
         np.testing.assert_array_equal(sts[i].infos()["iters"], s1.infos()["iters"])
 
 
-def test_gradients_match_oracle(api):
+@pytest.mark.parametrize("rng_mode", RANGES)
+def test_gradients_match_oracle(api, rng_mode):
     """Adjoint kernels vs the oracle's gradient formula at the same (fixed)
-    iteration count, and vs converged central differences of the oracle."""
-    _say("gradients")
+    iteration count."""
+    _say("gradients", rng_mode)
     rng = np.random.default_rng(11)
     n, m, d, r, eps = 300, 250, 3, 256, 0.7
     X = rng.standard_normal((n, d)).astype(np.float32)
@@ -256,7 +387,7 @@ def test_gradients_match_oracle(api):
     q = oracle.lambert_q(inputs.max_norm(X, Y), eps, d)
     U = inputs.gaussian_anchors(1, r, d, oracle.sigma2_from_q(q, eps))
     out, st = api.divergence(dev(X), dev(Y), dev(a), dev(b), dev(U), eps, q,
-                             fixed_iter=300)
+                             fixed_iter=300, range=rng_mode)
     dX, da, dY, db = [host(t) for t in api.divergence_backward(st)]
     rX, ra, rY, rb, div = oracle.divergence_grad(X, Y, a, b, U, eps, q,
                                                  fixed_iter=300)
@@ -266,15 +397,16 @@ def test_gradients_match_oracle(api):
         assert np.all(np.abs(gg - rr) <= GRAD_RTOL * np.abs(rr).max() * 10)
 
 
-def test_autograd_function(api):
+@pytest.mark.parametrize("rng_mode", RANGES)
+def test_autograd_function(api, rng_mode):
     """torch.autograd.Function wrapper: backward through the adjoint kernels,
     scaled by the incoming gradient."""
-    _say("autograd")
+    _say("autograd", rng_mode)
     c, U, eps, q = _divergence_inputs("gauss2d", n=400, m=300)
     X = dev(c.X).requires_grad_(True)
     a = dev(c.a).requires_grad_(True)
     W = api.sinkhorn_divergence(X, dev(c.Y), a, dev(c.b), dev(U), eps, q,
-                                fixed_iter=100)
+                                fixed_iter=100, range=rng_mode)
     (3.0 * W).backward()
     rX, ra, _, _, div = oracle.divergence_grad(c.X, c.Y, c.a, c.b, U, eps, q,
                                                fixed_iter=100)
@@ -285,20 +417,21 @@ def test_autograd_function(api):
     assert np.linalg.norm(ga - 3 * ra) / np.linalg.norm(3 * ra) <= GRAD_RTOL
 
 
-def test_status_codes(api):
+@pytest.mark.parametrize("rng_mode", RANGES)
+def test_status_codes(api, rng_mode):
     """Zero weights make a Sinkhorn division degenerate: SK_ERANGE is
     reported instead of silent NaNs.  An iteration cap below what the
     tolerance needs gives SK_ENOTCONV with the error reported."""
-    _say("status codes")
+    _say("status codes", rng_mode)
     c, U, eps, q = _divergence_inputs("gauss2d", n=200, m=200)
     a = c.a.copy()
     a[5] = 0.0
     out, st = api.divergence(dev(c.X), dev(c.Y), dev(a), dev(c.b), dev(U), eps,
-                             q, fixed_iter=10)
+                             q, fixed_iter=10, range=rng_mode)
     infos = st.infos()
     assert infos["status"][0] == 3 and infos["status"][1] == 3
     out, st = api.divergence(dev(c.X), dev(c.Y), dev(c.a), dev(c.b), dev(U),
-                             eps, q, tol=1e-12, max_iter=3)
+                             eps, q, tol=1e-12, max_iter=3, range=rng_mode)
     infos = st.infos()
     assert list(infos["status"]) == [4, 4, 4]
     assert list(infos["iters"]) == [3, 3, 3]
