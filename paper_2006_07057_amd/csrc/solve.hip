@@ -159,6 +159,20 @@ __device__ __forceinline__ float4 gld4(const float* p) {
   const nfloat4 v = *(gnfloat4*)p;
   return make_float4(v.x, v.y, v.z, v.w);
 }
+// Feature rows are read once per half-step: streaming (non-temporal) loads.
+constexpr bool kStreamLoads = true;
+__device__ __forceinline__ float4 gld4s(const float* p) {
+  nfloat4 v;
+  if (kStreamLoads) {
+    v = __builtin_nontemporal_load((gnfloat4*)p);
+  } else {
+    v = *(gnfloat4*)p;
+  }
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gst(float* p, float v) {
+  *(__attribute__((address_space(1))) float*)p = v;
+}
 
 // (E1, M1) + (E2, M2) in the extended-range representation.
 __device__ __forceinline__ void xr_combine(float& E1, float& M1, float E2,
@@ -249,12 +263,14 @@ __device__ __forceinline__ double block_dsum(double v, double* lds) {
 // ================================================================ linear
 // Lane layout: G lanes per row, each lane holding C float4 chunks at
 // columns 4*(lane%G) + 4*G*c; 64/G rows per wave load; U loads in flight.
-template <int G, int C, int U>
+// VL: the input r-vector lives in LDS (read per row) instead of registers;
+// W: occupancy target (waves per SIMD) that bounds the register budget.
+template <int G, int C, int U, bool VL, int W>
 struct LinearDomain {
+  static constexpr int kR = 4 * G * C;
   static constexpr int kLdsFloats = 4 * ((kWaves * G * C) > kBlock ? (kWaves * G * C) : kBlock);
   static constexpr int kVecStride = 1;  // floats per r-vector entry
-  // occupancy target (waves per SIMD) that bounds the register budget
-  static constexpr int kWavesPerEU = C <= 2 ? 4 : (C <= 4 ? 3 : (C <= 8 ? 2 : 1));
+  static constexpr int kWavesPerEU = W;
   static constexpr int kRowStride = 1;  // floats per scaling entry
 
   struct State {
@@ -262,20 +278,32 @@ struct LinearDomain {
     float4 acc[C];
   };
 
+  template <bool FRAMED>
   __device__ __forceinline__ static void zero(State& S) {
 #pragma unroll
     for (int c = 0; c < C; ++c) S.acc[c] = f4zero();
   }
 
-  // src: r floats
+  // src: r floats (into LDS, zero-padded to kR, when VL)
   __device__ __forceinline__ static void load_vec(const float* __restrict__ src, int r,
                                   State& S, float* lds) {
+    if (VL) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < kR; i += kBlock) lds[i] = i < r ? gld(src + i) : 0.f;
+      __syncthreads();
+      return;
+    }
     const int cl = (threadIdx.x & 63) % G;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int col = 4 * cl + 4 * G * c;
       S.vec[c] = col < r ? *reinterpret_cast<const float4*>(src + col) : f4zero();
     }
+  }
+  __device__ __forceinline__ static float4 vec_at(const State& S, const float* lds, int c,
+                                                  int cl) {
+    if (VL) return *reinterpret_cast<const float4*>(lds + 4 * cl + 4 * G * c);
+    return S.vec[c];
   }
 
   // sold/snew/target index rows; scalings are single floats.
@@ -291,7 +319,8 @@ struct LinearDomain {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int sub = lane / G;
     const int cl = lane % G;
-    const int64_t step = (int64_t)kWaves * U * RPW;
+    const int step = kWaves * U * RPW;
+    const int nrel = (int)(hi - lo);
 
     // Rows past `hi` load row hi-1 (always valid) and are neutralised with a
     // zero coefficient; masked columns meet a zero entry of the r-vector and
@@ -309,17 +338,18 @@ struct LinearDomain {
       const int col = 4 * cl + 4 * G * c;
       coff[c] = col < r ? col : 0;
     }
-    auto load = [&](Batch& B, int64_t base) {
+    auto load = [&](Batch& B, int rel) {
+      const int64_t base = lo + rel;
       const float* pb = P + base * (int64_t)r;
-      const int64_t rem64 = hi - base;
-      const int rem = rem64 < U * RPW ? (int)rem64 : U * RPW;
+      const int rem0 = nrel - rel;
+      const int rem = rem0 < U * RPW ? rem0 : U * RPW;
 #pragma unroll
       for (int uu = 0; uu < U; ++uu) {
         const int rr = uu * RPW + sub;
         const int rc = rr < rem ? rr : rem - 1;
         const float* prow = pb + rc * r;
 #pragma unroll
-        for (int c = 0; c < C; ++c) B.x[uu][c] = gld4(prow + coff[c]);
+        for (int c = 0; c < C; ++c) B.x[uu][c] = gld4s(prow + coff[c]);
         if (MODE == MODE_ACCUM) {
           B.tw[uu] = sold ? gld(sold + base + rc) : 1.0f;
         } else {
@@ -329,8 +359,9 @@ struct LinearDomain {
           B.to[uu] = gld(sold + base + rc);
       }
     };
-    auto process = [&](const Batch& B, int64_t base) {
-      const int64_t rem = hi - base;
+    auto process = [&](const Batch& B, int rel) {
+      const int64_t base = lo + rel;
+      const int rem = nrel - rel;
 #pragma unroll
       for (int uu = 0; uu < U; ++uu) {
         const int rr = uu * RPW + sub;
@@ -342,7 +373,7 @@ struct LinearDomain {
         } else {
           float t = 0.0f;
 #pragma unroll
-          for (int c = 0; c < C; ++c) t = f4dot(B.x[uu][c], S.vec[c], t);
+          for (int c = 0; c < C; ++c) t = f4dot(B.x[uu][c], vec_at(S, lds, c, cl), t);
           t = dpp_sum<G>(t);
           if (MODE == MODE_UPDATE_CHECK || MODE == MODE_CHECK) {
             if (rv && cl == 0)
@@ -352,7 +383,7 @@ struct LinearDomain {
             const float nv = B.tw[uu] / t;
             if (rv) {
               if (!(t > 0.0f) || !(nv > 0.0f) || !isfinite(nv)) bad = 1;
-              if (cl == 0) snew[row] = nv;
+              if (cl == 0) gst(snew + row, nv);
             }
             coef = rv ? nv : 0.0f;
           } else {
@@ -366,27 +397,33 @@ struct LinearDomain {
       }
     };
     // software pipeline: the next batch is in flight while one is processed
-    int64_t base = lo + (int64_t)wave * U * RPW;
-    if (base >= hi) return;
+    // The next batch is always loaded (past the end: the current batch
+    // again, in bounds and unused), so the loop body is straight-line code
+    // and each wait covers only the batch about to be processed.  Row
+    // indices are 32-bit offsets from lo (a workgroup's share of rows is
+    // far below 2^31), so the bounds tests stay in scalar registers.
+    int rel = wave * U * RPW;
+    if (rel >= nrel) return;
     Batch A, Bb;
-    load(A, base);
+    load(A, rel);
     for (;;) {
-      int64_t nb = base + step;
-      if (nb < hi) load(Bb, nb);
-      process(A, base);
-      if (nb >= hi) break;
-      base = nb;
-      nb = base + step;
-      if (nb < hi) load(A, nb);
-      process(Bb, base);
-      if (nb >= hi) break;
-      base = nb;
+      int nr = rel + step;
+      load(Bb, nr < nrel ? nr : rel);
+      process(A, rel);
+      if (nr >= nrel) break;
+      rel = nr;
+      nr = rel + step;
+      load(A, nr < nrel ? nr : rel);
+      process(Bb, rel);
+      if (nr >= nrel) break;
+      rel = nr;
     }
   }
 
   // Sum the per-lane accumulators of the workgroup into out (r floats).
+  template <bool FRAMED>
   __device__ __forceinline__ static void block_store(State& S, float* __restrict__ out, int r,
-                                     float* ldsf) {
+                                                     float* ldsf, const float*, bool) {
     float4* lds = reinterpret_cast<float4*>(ldsf);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -424,11 +461,13 @@ struct LinearDomain {
 
   // Workgroup br of a group of g sums its slice of float4 columns over the
   // g workgroup partials (fixed order: by seat) and writes them to out.
+  template <bool FRAMED>
   __device__ __forceinline__ static void column_reduce(const float* __restrict__ slots,
-                                       int slot_stride,
-                                       const int32_t* __restrict__ members,
-                                       int g, int r, int br,
-                                       float* __restrict__ out, float* ldsf) {
+                                                       int slot_stride,
+                                                       const int32_t* __restrict__ members,
+                                                       int g, int r, int br,
+                                                       float* __restrict__ out, float* ldsf,
+                                                       const float*) {
     float4* lds = reinterpret_cast<float4*>(ldsf);
     const int r4 = r >> 2;
     const int per = (r4 + g - 1) / g;
@@ -475,48 +514,81 @@ struct LinearDomain {
 };
 
 // ======================================================== extended range
-template <int G, int C, int U>
+// Features are log2 values L <= 0; scalings and r-vectors are pairs (E, M)
+// meaning M * 2^E, stored as two halves [E(len) | M(len)].
+//
+// Update passes (input r-vector z = zM * 2^zE):
+//   dot side, per row:   mx = ceil(max_k (L_k + zE_k)),
+//                        e_k = 2^(L_k + zE_k - mx) in (0, 1],
+//                        t = 2^mx * sum_k e_k zM_k;   new scaling (-mx, target/sum)
+//   accumulation side:   the new r-vector entry k is
+//                        sum_rows newM * 2^(L_k - mx) = 2^(-zE_k) * sum_rows newM e_k,
+//                        so it is accumulated as a plain float32 sum of newM * e_k
+//                        in the per-column frame 2^(-zE_k) and converted to a pair
+//                        once, after the cross-workgroup reduction.
+// One exp2 per element serves both sides.  In that frame a row adds
+// target * e_k zM_k / (zM_k sum) <= target / zM_k, so a column's frame value is
+// the share of the total target mass carried by anchor k divided by zM_k:
+// never above 2 (the weights sum to one, zM is in [0.5, 1)); columns whose
+// share is below the float32 range carry no mass at float32 precision.
+//
+// The first pass (z^(0) = Prow^T u^(0)) has no input frame: it keeps a
+// per-column exponent in every lane, raised on the fly, and reduces pairs.
+template <int G, int C, int U, bool VL, int W>
 struct XRangeDomain {
-  // LDS: the r-vector (2r floats) during a pass, then the workgroup
-  // reduction buffer (kWaves x r pairs).
   static constexpr int kR = 4 * G * C;
   static constexpr int kLdsFloats =
       (2 * kWaves * kR) > (4 * kBlock) ? (2 * kWaves * kR) : (4 * kBlock);
   static constexpr int kVecStride = 2;
-  static constexpr int kWavesPerEU = C <= 2 ? 3 : (C <= 4 ? 2 : 1);
+  static constexpr int kWavesPerEU = W;
   static constexpr int kRowStride = 2;
 
   struct State {
-    float4 accE[C];
-    float4 accM[C];
+    float4 vecE[C];   // input r-vector, lane's columns (update passes)
+    float4 vecM[C];
+    float4 accE[C];   // first pass only: per-column exponent
+    float4 accM[C];   // first pass: mantissas; update passes: frame sums
   };
 
+  template <bool FRAMED>
   __device__ __forceinline__ static void zero(State& S) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      S.accE[c] = f4fill(kNegBig);
+      if (!FRAMED) S.accE[c] = f4fill(kNegBig);
       S.accM[c] = f4zero();
     }
   }
 
-  // src: [E(r) | M(r)] -> LDS as [E(kR) | M(kR)], padded with zero entries
-  // (E = kNegBig, M = 0) so every lane column has a defined value.
+  // src: [E(r) | M(r)] -> the lane's columns; columns >= r read as the zero
+  // entry (E = kNegBig, M = 0).
   __device__ __forceinline__ static void load_vec(const float* __restrict__ src, int r,
-                                  State&, float* lds) {
-    __syncthreads();
-    gfloat* s = gp(src);
-    for (int i = threadIdx.x; i < kR; i += kBlock) {
-      const bool ok = i < r;
-      lds[i] = ok ? s[i] : kNegBig;
-      lds[kR + i] = ok ? s[r + i] : 0.f;
+                                                  State& S, float* lds) {
+    if (VL) {  // LDS: [E(kR) | M(kR)]
+      __syncthreads();
+      for (int i = threadIdx.x; i < kR; i += kBlock) {
+        const bool ok = i < r;
+        lds[i] = ok ? gld(src + i) : kNegBig;
+        lds[kR + i] = ok ? gld(src + r + i) : 0.f;
+      }
+      __syncthreads();
+      return;
     }
-    __syncthreads();
+    const int cl = (threadIdx.x & 63) % G;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int col = 4 * cl + 4 * G * c;
+      const bool ok = col < r;
+      const int cc = ok ? col : 0;
+      const float4 e = gld4(src + cc);
+      const float4 m = gld4(src + r + cc);
+      S.vecE[c] = ok ? e : f4fill(kNegBig);
+      S.vecM[c] = ok ? m : f4zero();
+    }
   }
 
-  // acc_k += rowM * 2^(rowE + x_k) for the lane's columns.  The column
-  // exponent starts at the first valid row (exactly, from ceil(x_k)) and is
-  // raised when a term would exceed 2^0 relative to it; invalid rows come
-  // with rowE = kNegBig, rowM = 0 and add nothing.
+  // First pass: acc_k += rowM * 2^(rowE + x_k) with a per-column exponent
+  // that starts at the first valid row and is raised when a term would
+  // exceed it.  Invalid rows come with rv = false and add nothing.
   __device__ __forceinline__ static void accum_row(State& S, const float4 (&x)[C],
                                                    float rowE, float rowM,
                                                    bool rv, bool& started) {
@@ -545,7 +617,7 @@ struct XRangeDomain {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         float xx = xv[q] + (rowE - E[q]);
-        if (xx > 0.f) {  // raise the column exponent (rare after warm-up)
+        if (xx > 0.f) {
           const float cc = ceilf(xx);
           M[q] = xldexp(M[q], -cc);
           E[q] += cc;
@@ -570,15 +642,14 @@ struct XRangeDomain {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int sub = lane / G;
     const int cl = lane % G;
-    const float* vE = lds;
-    const float* vM = lds + kR;
-    const int64_t step = (int64_t)kWaves * U * RPW;
+    const int step = kWaves * U * RPW;
+    const int nrel = (int)(hi - lo);
 
     bool started = false;
     // Loads are unconditional: rows past `hi` read row hi-1, masked columns
     // read column 0; both are neutralised afterwards (zero weight, or the
-    // padded r-vector entry 2^kNegBig * 0).  Addresses: wave-uniform batch
-    // base plus a small 32-bit per-lane offset.
+    // zero r-vector entry).  Addresses: wave-uniform batch base plus a small
+    // 32-bit per-lane offset.
     struct Batch {
       float4 x[U][C];
       float tw[U], toE[U], toM[U];
@@ -589,17 +660,18 @@ struct XRangeDomain {
       const int col = 4 * cl + 4 * G * c;
       coff[c] = col < r ? col : 0;
     }
-    auto load = [&](Batch& B, int64_t base) {
+    auto load = [&](Batch& B, int rel) {
+      const int64_t base = lo + rel;
       const float* pb = P + base * (int64_t)r;
-      const int64_t rem64 = hi - base;
-      const int rem = rem64 < U * RPW ? (int)rem64 : U * RPW;
+      const int rem0 = nrel - rel;
+      const int rem = rem0 < U * RPW ? rem0 : U * RPW;
 #pragma unroll
       for (int uu = 0; uu < U; ++uu) {
         const int rr = uu * RPW + sub;
         const int rc = rr < rem ? rr : rem - 1;
         const float* prow = pb + rc * r;
 #pragma unroll
-        for (int c = 0; c < C; ++c) B.x[uu][c] = gld4(prow + coff[c]);
+        for (int c = 0; c < C; ++c) B.x[uu][c] = gld4s(prow + coff[c]);
         if (MODE == MODE_ACCUM) {
           B.toE[uu] = sold ? gld(sold + base + rc) : 0.0f;
           B.toM[uu] = sold ? gld(sold + nrows + base + rc) : 1.0f;
@@ -612,96 +684,155 @@ struct XRangeDomain {
         }
       }
     };
-    auto process = [&](const Batch& B, int64_t base) {
-      const int64_t rem = hi - base;
+    auto process = [&](const Batch& B, int rel) {
+      const int64_t base = lo + rel;
+      const int rem = nrel - rel;
 #pragma unroll
       for (int uu = 0; uu < U; ++uu) {
         const int rr = uu * RPW + sub;
         const int64_t row = base + rr;
         const bool rv = rr < rem;
-        float rowE = kNegBig, rowM = 0.f;
         if (MODE == MODE_ACCUM) {
-          if (rv) {
-            rowE = B.toE[uu];
-            rowM = B.toM[uu];
-          }
-        } else {
-          // dot side: t = sum_k 2^(x_k + zE_k) zM_k = 2^mx * ssum
-          float mx = kNegBig;
+          accum_row(S, B.x[uu], rv ? B.toE[uu] : kNegBig, rv ? B.toM[uu] : 0.f,
+                    rv, started);
+          continue;
+        }
+        // e_k = 2^(x_k + zE_k - mx), computed in place
+        float4 e[C];
+        float mx = kNegBig;
 #pragma unroll
-          for (int c = 0; c < C; ++c) {
-            const int col = 4 * cl + 4 * G * c;
-            const float4 e4 = *reinterpret_cast<const float4*>(vE + col);
-            const float4& xv = B.x[uu][c];
-            mx = fmaxf(mx, fmaxf(fmaxf(xv.x + e4.x, xv.y + e4.y),
-                                 fmaxf(xv.z + e4.z, xv.w + e4.w)));
-          }
-          mx = ceilf(dpp_max<G>(mx));
-          float ssum = 0.f;
+        for (int c = 0; c < C; ++c) {
+          const float4& xv = B.x[uu][c];
+          const float4 zE = VL ? *reinterpret_cast<const float4*>(lds + 4 * cl + 4 * G * c)
+                               : S.vecE[c];
+          e[c].x = xv.x + zE.x;
+          e[c].y = xv.y + zE.y;
+          e[c].z = xv.z + zE.z;
+          e[c].w = xv.w + zE.w;
+          mx = fmaxf(mx, fmaxf(fmaxf(e[c].x, e[c].y), fmaxf(e[c].z, e[c].w)));
+        }
+        mx = ceilf(dpp_max<G>(mx));
+        float ssum = 0.f;
 #pragma unroll
-          for (int c = 0; c < C; ++c) {
-            const int col = 4 * cl + 4 * G * c;
-            const float4 e4 = *reinterpret_cast<const float4*>(vE + col);
-            const float4 m4 = *reinterpret_cast<const float4*>(vM + col);
-            const float4& xv = B.x[uu][c];
-            ssum = fmaf(xexp2(xv.x + (e4.x - mx)), m4.x, ssum);
-            ssum = fmaf(xexp2(xv.y + (e4.y - mx)), m4.y, ssum);
-            ssum = fmaf(xexp2(xv.z + (e4.z - mx)), m4.z, ssum);
-            ssum = fmaf(xexp2(xv.w + (e4.w - mx)), m4.w, ssum);
-          }
-          ssum = dpp_sum<G>(ssum);
-          if (MODE == MODE_UPDATE_CHECK || MODE == MODE_CHECK) {
-            if (rv && cl == 0) {
-              const double prod = (double)B.toM[uu] * (double)ssum;
-              const double ex = (double)B.toE[uu] + (double)mx;
-              err += fabs(ldexp(prod, (int)fmax(fmin(ex, 2000.0), -2000.0)) -
-                          (double)B.tw[uu]);
-            }
-          }
-          if (MODE != MODE_CHECK) {
-            const float nm = B.tw[uu] / ssum;
-            const float ne = -mx;
-            if (rv) {
-              if (!(ssum > 0.0f) || !(nm > 0.0f) || !isfinite(nm) ||
-                  !(mx > -1.0e7f) || !(mx < 1.0e7f))
-                bad = 1;
-              if (cl == 0) {
-                snew[row] = ne;
-                snew[nrows + row] = nm;
-              }
-              rowE = ne;
-              rowM = nm;
-            }
-          } else {
-            if (rv && !(ssum > 0.0f)) bad = 1;
+        for (int c = 0; c < C; ++c) {
+          e[c].x = xexp2(e[c].x - mx);
+          e[c].y = xexp2(e[c].y - mx);
+          e[c].z = xexp2(e[c].z - mx);
+          e[c].w = xexp2(e[c].w - mx);
+          const float4 zM = VL ? *reinterpret_cast<const float4*>(lds + kR + 4 * cl + 4 * G * c)
+                               : S.vecM[c];
+          ssum = f4dot(e[c], zM, ssum);
+        }
+        ssum = dpp_sum<G>(ssum);
+        if (MODE == MODE_UPDATE_CHECK || MODE == MODE_CHECK) {
+          if (rv && cl == 0) {
+            const double prod = (double)B.toM[uu] * (double)ssum;
+            const double ex = (double)B.toE[uu] + (double)mx;
+            err += fabs(ldexp(prod, (int)fmax(fmin(ex, 2000.0), -2000.0)) -
+                        (double)B.tw[uu]);
           }
         }
-        if (MODE != MODE_CHECK) accum_row(S, B.x[uu], rowE, rowM, rv, started);
+        if (MODE != MODE_CHECK) {
+          const float nm = B.tw[uu] / ssum;
+          if (rv) {
+            if (!(ssum > 0.0f) || !(nm > 0.0f) || !isfinite(nm) ||
+                !(mx > -1.0e7f) || !(mx < 1.0e7f))
+              bad = 1;
+            if (cl == 0) {
+              gst(snew + row, -mx);
+              gst(snew + nrows + row, nm);
+            }
+          }
+          const float coef = rv ? nm : 0.0f;
+#pragma unroll
+          for (int c = 0; c < C; ++c) f4fma(S.accM[c], coef, e[c]);
+        } else {
+          if (rv && !(ssum > 0.0f)) bad = 1;
+        }
       }
     };
-    int64_t base = lo + (int64_t)wave * U * RPW;
-    if (base >= hi) return;
+    // The next batch is always loaded (past the end: the current batch
+    // again, in bounds and unused), so the loop body is straight-line code
+    // and each wait covers only the batch about to be processed.  Row
+    // indices are 32-bit offsets from lo (a workgroup's share of rows is
+    // far below 2^31), so the bounds tests stay in scalar registers.
+    int rel = wave * U * RPW;
+    if (rel >= nrel) return;
     Batch A, Bb;
-    load(A, base);
+    load(A, rel);
     for (;;) {
-      int64_t nb = base + step;
-      if (nb < hi) load(Bb, nb);
-      process(A, base);
-      if (nb >= hi) break;
-      base = nb;
-      nb = base + step;
-      if (nb < hi) load(A, nb);
-      process(Bb, base);
-      if (nb >= hi) break;
-      base = nb;
+      int nr = rel + step;
+      load(Bb, nr < nrel ? nr : rel);
+      process(A, rel);
+      if (nr >= nrel) break;
+      rel = nr;
+      nr = rel + step;
+      load(A, nr < nrel ? nr : rel);
+      process(Bb, rel);
+      if (nr >= nrel) break;
+      rel = nr;
     }
   }
 
-  // Combine the lanes' (E, M) accumulators into out = [E(r) | M(r)].
+  // (E, M) of the value tot * 2^(-fE) with the mantissa in [0.5, 1).
+  __device__ __forceinline__ static void frame_to_pair(float tot, float fE, float& E,
+                                                       float& M) {
+    if (tot > 0.f) {
+      int ex = 0;
+      M = frexpf(tot, &ex);
+      E = (float)ex - fE;
+    } else {
+      E = kNegBig;
+      M = 0.f;
+    }
+  }
+
+  // Combine the lanes' accumulators of the workgroup.  First pass: pairs
+  // [E(r) | M(r)].  Update passes: frame sums (r floats) into a slot, or,
+  // when `final` (single-workgroup solve), pairs converted with the input
+  // r-vector `frame` ([E | M], only E is used).
+  template <bool FRAMED>
   __device__ __forceinline__ static void block_store(State& S, float* __restrict__ out, int r,
-                                     float* lds) {
+                                                     float* lds, const float* frame,
+                                                     bool final) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (FRAMED) {
+#pragma unroll
+      for (int off = G; off < 64; off <<= 1) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          S.accM[c].x += __shfl_xor(S.accM[c].x, off, 64);
+          S.accM[c].y += __shfl_xor(S.accM[c].y, off, 64);
+          S.accM[c].z += __shfl_xor(S.accM[c].z, off, 64);
+          S.accM[c].w += __shfl_xor(S.accM[c].w, off, 64);
+        }
+      }
+      __syncthreads();
+      if (lane < G) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const int col = 4 * lane + 4 * G * c;
+          if (col < r) *reinterpret_cast<float4*>(lds + wave * r + col) = S.accM[c];
+        }
+      }
+      __syncthreads();
+      for (int col = threadIdx.x; col < r; col += kBlock) {
+        float s = lds[col];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) s += lds[w * r + col];
+        if (final) {
+          float E, M;
+          frame_to_pair(s, frame[col], E, M);
+          out[col] = E;
+          out[r + col] = M;
+        } else {
+          out[col] = s;
+        }
+      }
+      __syncthreads();
+      return;
+    }
 #pragma unroll
     for (int off = G; off < 64; off <<= 1) {
 #pragma unroll
@@ -721,7 +852,7 @@ struct XRangeDomain {
         }
       }
     }
-    __syncthreads();  // the r-vector in LDS is no longer needed
+    __syncthreads();
     if (lane < G) {
 #pragma unroll
       for (int c = 0; c < C; ++c) {
@@ -744,11 +875,15 @@ struct XRangeDomain {
     __syncthreads();
   }
 
+  // Workgroup br of a group of g reduces its slice of columns over the g
+  // workgroup partials (fixed order: by seat) and writes pairs to out.
+  template <bool FRAMED>
   __device__ __forceinline__ static void column_reduce(const float* __restrict__ slots,
-                                       int slot_stride,
-                                       const int32_t* __restrict__ members,
-                                       int g, int r, int br,
-                                       float* __restrict__ out, float* lds) {
+                                                       int slot_stride,
+                                                       const int32_t* __restrict__ members,
+                                                       int g, int r, int br,
+                                                       float* __restrict__ out, float* lds,
+                                                       const float* frame) {
     const int per = (r + g - 1) / g;
     const int c0 = br * per;
     const int c1 = min(r, c0 + per);
@@ -762,7 +897,11 @@ struct XRangeDomain {
       if (split < Sn) {
         for (int b = split; b < g; b += Sn) {
           const float* p = slots + (int64_t)members[b] * slot_stride;
-          xr_combine(e, m, p[col], p[r + col]);
+          if (FRAMED) {
+            m += p[col];
+          } else {
+            xr_combine(e, m, p[col], p[r + col]);
+          }
         }
       }
       lds[t] = e;
@@ -770,9 +909,16 @@ struct XRangeDomain {
       __syncthreads();
       if (t < nc) {
         float te = lds[t], tm = lds[kBlock + t];
-        for (int k = 1; k < Sn; ++k)
-          xr_combine(te, tm, lds[t + k * nc], lds[kBlock + t + k * nc]);
-        if (tm > 0.f) {  // normalise the mantissa to [0.5, 1)
+        for (int k = 1; k < Sn; ++k) {
+          if (FRAMED) {
+            tm += lds[kBlock + t + k * nc];
+          } else {
+            xr_combine(te, tm, lds[t + k * nc], lds[kBlock + t + k * nc]);
+          }
+        }
+        if (FRAMED) {
+          frame_to_pair(tm, frame[col], te, tm);
+        } else if (tm > 0.f) {  // normalise the mantissa to [0.5, 1)
           int ex = 0;
           tm = frexpf(tm, &ex);
           te += (float)ex;
@@ -803,19 +949,22 @@ struct Shared {
 // Reduce a half-step's accumulators into dst (directly when g == 1, else via
 // workgroup partials + barrier + column slice), publish (err, bad) and
 // return the group totals through err/bad.  Returns false if aborted.
-template <class Dom>
+// FRAMED: update pass whose accumulators are relative to the input r-vector
+// `frame` (extended range); otherwise the first pass.
+template <class Dom, bool FRAMED>
 __device__ __forceinline__ bool finish_half_step(
     const SolveDesc& D, int br, BarrierState& B, typename Dom::State& S,
-    float* __restrict__ dst, bool reduce_vec, double& err, int& bad,
-    float* lds, Shared& sh) {
+    float* __restrict__ dst, bool reduce_vec, const float* frame, double& err,
+    int& bad, float* lds, Shared& sh) {
   const int g = D.g;
   const double e_blk = block_dsum(err, sh.d);
   const double b_blk = block_dsum((double)bad, sh.d);
   if (reduce_vec) {
     if (g == 1) {
-      Dom::block_store(S, dst, D.r, lds);
+      Dom::template block_store<FRAMED>(S, dst, D.r, lds, frame, true);
     } else {
-      Dom::block_store(S, D.slots + (int64_t)blockIdx.x * D.slot_stride, D.r, lds);
+      Dom::template block_store<FRAMED>(
+          S, D.slots + (int64_t)blockIdx.x * D.slot_stride, D.r, lds, frame, false);
     }
   }
   if (threadIdx.x == 0) {
@@ -825,7 +974,8 @@ __device__ __forceinline__ bool finish_half_step(
   if (!group_barrier(B)) return false;
   if (g > 1) {
     if (reduce_vec)
-      Dom::column_reduce(D.slots, D.slot_stride, D.members, g, D.r, br, dst, lds);
+      Dom::template column_reduce<FRAMED>(D.slots, D.slot_stride, D.members, g, D.r,
+                                          br, dst, lds, frame);
     err = group_dsum(D.dpart, g, sh.d);
     bad = group_dsum(D.dpart + g, g, sh.d) > 0.0 ? 1 : 0;
     if (!group_barrier(B)) return false;
@@ -878,13 +1028,14 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
   if (threadIdx.x == 0) D.members[br] = (int32_t)blockIdx.x;
 
   // z^(0) = Prow^T u^(0), u^(0) = 1 or the caller's start.
-  Dom::zero(S);
+  Dom::template zero<false>(S);
   Dom::template half_step<MODE_ACCUM>(uniform_ptr(D.Prow), rlo(), rhi(), r,
                                       uniform_i64(D.n), S, nullptr,
                                       D.warm ? uniform_ptr(D.u) : nullptr,
                                       nullptr, err, bad, lds);
   err = 0.0;
-  ok = finish_half_step<Dom>(D, br, B, S, uniform_ptr(D.z), true, err, bad, lds, sh);
+  ok = finish_half_step<Dom, false>(D, br, B, S, uniform_ptr(D.z), true, nullptr, err,
+                                    bad, lds, sh);
 
   int status = SK_OK;
   int kf = 0;
@@ -896,7 +1047,7 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
   for (int k = 1; ok && status == SK_OK; ++k) {
     const bool last = k > limit;
     Dom::load_vec(uniform_ptr(D.z), r, S, lds);
-    Dom::zero(S);
+    Dom::template zero<true>(S);
     err = 0.0;
     bad = 0;
     if (last) {
@@ -914,7 +1065,8 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
                                            uniform_i64(D.m), S, uniform_ptr(D.b),
                                            nullptr, vbuf(k), err, bad, lds);
     }
-    ok = finish_half_step<Dom>(D, br, B, S, wbuf(k), !last, err, bad, lds, sh);
+    ok = finish_half_step<Dom, true>(D, br, B, S, wbuf(k), !last, uniform_ptr(D.z), err,
+                                     bad, lds, sh);
     if (!ok) break;
     if (k >= 2) err_final = err;  // error of iteration k-1
     if (bad) {
@@ -933,13 +1085,14 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
     }
     // u-half-step with w^(k).
     Dom::load_vec(wbuf(k), r, S, lds);
-    Dom::zero(S);
+    Dom::template zero<true>(S);
     err = 0.0;
     bad = 0;
     Dom::template half_step<MODE_UPDATE>(uniform_ptr(D.Prow), rlo(), rhi(), r,
                                          uniform_i64(D.n), S, uniform_ptr(D.a),
                                          nullptr, uniform_ptr(D.u), err, bad, lds);
-    ok = finish_half_step<Dom>(D, br, B, S, uniform_ptr(D.z), true, err, bad, lds, sh);
+    ok = finish_half_step<Dom, true>(D, br, B, S, uniform_ptr(D.z), true, wbuf(k), err,
+                                     bad, lds, sh);
     if (!ok) break;
     if (bad) {
       status = SK_ERANGE;
@@ -1074,18 +1227,31 @@ void launch_cls(dim3 grid, hipStream_t s, const SolveDesc* d, int count,
                      seats, ctl, tl);
 }
 
-#define SK_CLASS(G, C, U, UX)                                                \
-  {4 * (G) * (C),                                                            \
-   {reinterpret_cast<const void*>(&solver_kernel<LinearDomain<G, C, U>>),    \
-    reinterpret_cast<const void*>(&solver_kernel<XRangeDomain<G, C, UX>>)},  \
-   {&launch_cls<LinearDomain<G, C, U>>, &launch_cls<XRangeDomain<G, C, UX>>}}
+// A class serves every r <= rmax with one linear and one extended-range
+// kernel; each kernel's lane layout (G lanes per row, C float4 per lane, so
+// 4 G C >= rmax), batch depth U, r-vector placement VL and occupancy W.
+#define SK_CLASS(RMAX, LG, LC, LU, LV, LW, XG, XC, XU, XV, XW)                        \
+  {RMAX,                                                                            \
+   {reinterpret_cast<const void*>(&solver_kernel<LinearDomain<LG, LC, LU, LV, LW>>), \
+    reinterpret_cast<const void*>(&solver_kernel<XRangeDomain<XG, XC, XU, XV, XW>>)}, \
+   {&launch_cls<LinearDomain<LG, LC, LU, LV, LW>>,                                   \
+    &launch_cls<XRangeDomain<XG, XC, XU, XV, XW>>}}
 
 const SolverClass kClasses[] = {
-    SK_CLASS(1, 1, 2, 2),   SK_CLASS(2, 1, 2, 2),   SK_CLASS(4, 1, 2, 2),
-    SK_CLASS(8, 1, 2, 2),   SK_CLASS(16, 1, 2, 2),  SK_CLASS(32, 1, 2, 2),
-    SK_CLASS(64, 1, 2, 2),  SK_CLASS(64, 2, 2, 1),  SK_CLASS(64, 3, 1, 1),
-    SK_CLASS(64, 4, 1, 1),  SK_CLASS(64, 6, 1, 1),  SK_CLASS(64, 8, 1, 1),
-    SK_CLASS(64, 12, 1, 1), SK_CLASS(64, 16, 1, 1),
+    SK_CLASS(4, 1, 1, 2, true, 4, 1, 1, 2, true, 4),
+    SK_CLASS(8, 1, 2, 2, true, 2, 1, 2, 2, true, 2),
+    SK_CLASS(16, 1, 4, 2, true, 2, 1, 4, 2, true, 2),
+    SK_CLASS(32, 1, 8, 2, true, 1, 1, 8, 2, true, 1),
+    SK_CLASS(64, 2, 8, 2, true, 1, 2, 8, 2, true, 1),
+    SK_CLASS(128, 4, 8, 2, true, 1, 4, 8, 2, true, 1),
+    SK_CLASS(256, 8, 8, 2, true, 1, 8, 8, 2, true, 1),
+    SK_CLASS(512, 16, 8, 2, true, 1, 16, 8, 2, true, 1),
+    SK_CLASS(768, 32, 6, 2, true, 1, 32, 6, 2, true, 1),
+    SK_CLASS(1024, 32, 8, 2, true, 1, 32, 8, 2, true, 1),
+    SK_CLASS(1536, 64, 6, 2, true, 1, 64, 6, 2, true, 1),
+    SK_CLASS(2048, 64, 8, 2, true, 1, 64, 8, 2, true, 1),
+    SK_CLASS(3072, 64, 12, 1, false, 1, 64, 12, 1, false, 1),
+    SK_CLASS(4096, 64, 16, 1, false, 1, 64, 16, 1, false, 1),
 };
 constexpr int kNumClasses = sizeof(kClasses) / sizeof(kClasses[0]);
 
