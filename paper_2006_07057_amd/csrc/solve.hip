@@ -174,6 +174,30 @@ __device__ __forceinline__ void gst(float* p, float v) {
   *(__attribute__((address_space(1))) float*)p = v;
 }
 
+// Data shared between the workgroups of a solve (partial slots, reduced
+// r-vectors, float64 partials, the member table) is written and read with
+// relaxed agent-scope atomics.  Those accesses are coherent across the
+// chip's per-XCD L2 caches by themselves, so the workgroup barrier needs no
+// device-scope fence (a fence writes back and invalidates whole caches).
+// Scalings are private to the workgroup that owns their rows.
+template <class T>
+__device__ __forceinline__ T cld(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void cst(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float4 cld4(const float* p) {
+  return make_float4(cld(p), cld(p + 1), cld(p + 2), cld(p + 3));
+}
+__device__ __forceinline__ void cst4(float* p, const float4& v) {
+  cst(p, v.x);
+  cst(p + 1, v.y);
+  cst(p + 2, v.z);
+  cst(p + 3, v.w);
+}
+
 // (E1, M1) + (E2, M2) in the extended-range representation.
 __device__ __forceinline__ void xr_combine(float& E1, float& M1, float E2,
                                            float M2) {
@@ -194,21 +218,22 @@ struct BarrierState {
 };
 
 // All threads of the workgroup call this.  Returns false if the launch was
-// aborted (time-out here or elsewhere).
+// aborted (time-out here or elsewhere).  Every store a workgroup makes for
+// the others is agent-coherent; waiting for all of them to complete (every
+// wave) before the arrival is counted orders them before any load another
+// workgroup issues after seeing the count.
 __device__ __forceinline__ bool group_barrier(BarrierState& B) {
   __shared__ int s_ok;
-  __threadfence();  // release this thread's writes at device scope
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   B.target += B.g;
-  if (B.g == 1) {
-    __threadfence();
-    return true;
-  }
+  if (B.g == 1) return true;
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(B.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(B.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
     const uint64_t t0 = wall_clock64();
-    while (__hip_atomic_load(B.bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+    while (__hip_atomic_load(B.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
            B.target) {
       if (__hip_atomic_load(B.abort_flag, __ATOMIC_RELAXED,
                             __HIP_MEMORY_SCOPE_AGENT) != 0u) {
@@ -226,7 +251,7 @@ __device__ __forceinline__ bool group_barrier(BarrierState& B) {
     s_ok = ok;
   }
   __syncthreads();
-  __threadfence();  // acquire for every thread of the workgroup
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
   const bool ok = s_ok != 0;
   __syncthreads();
   return ok;
@@ -236,7 +261,7 @@ __device__ __forceinline__ bool group_barrier(BarrierState& B) {
 __device__ __forceinline__ double group_dsum(const double* __restrict__ src,
                                              int g, double* lds) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < g; i += kBlock) s += src[i];
+  for (int i = threadIdx.x; i < g; i += kBlock) s += cld(src + i);
   lds[threadIdx.x] = s;
   __syncthreads();
   for (int off = kBlock / 2; off > 0; off >>= 1) {
@@ -289,7 +314,7 @@ struct LinearDomain {
                                   State& S, float* lds) {
     if (VL) {
       __syncthreads();
-      for (int i = threadIdx.x; i < kR; i += kBlock) lds[i] = i < r ? gld(src + i) : 0.f;
+      for (int i = threadIdx.x; i < kR; i += kBlock) lds[i] = i < r ? cld(src + i) : 0.f;
       __syncthreads();
       return;
     }
@@ -297,7 +322,7 @@ struct LinearDomain {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int col = 4 * cl + 4 * G * c;
-      S.vec[c] = col < r ? *reinterpret_cast<const float4*>(src + col) : f4zero();
+      S.vec[c] = col < r ? cld4(src + col) : f4zero();
     }
   }
   __device__ __forceinline__ static float4 vec_at(const State& S, const float* lds, int c,
@@ -454,7 +479,7 @@ struct LinearDomain {
         const float4 t = lds[w * r4 + c4];
         s.x += t.x; s.y += t.y; s.z += t.z; s.w += t.w;
       }
-      reinterpret_cast<float4*>(out)[c4] = s;
+      cst4(out + 4 * c4, s);
     }
     __syncthreads();
   }
@@ -473,7 +498,6 @@ struct LinearDomain {
     const int per = (r4 + g - 1) / g;
     const int c0 = br * per;
     const int c1 = min(r4, c0 + per);
-    float4* o4 = reinterpret_cast<float4*>(out);
     for (int cc = c0; cc < c1; cc += kBlock) {
       const int nc = min(kBlock, c1 - cc);
       const int Sn = kBlock / nc;
@@ -483,9 +507,8 @@ struct LinearDomain {
       float4 s = f4zero();
       if (split < Sn) {
         for (int b = split; b < g; b += Sn) {
-          const float4* p4 = reinterpret_cast<const float4*>(
-              slots + (int64_t)members[b] * slot_stride);
-          const float4 v = p4[col];
+          const float4 v =
+              cld4(slots + (int64_t)cld(members + b) * slot_stride + 4 * col);
           s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
         }
       }
@@ -497,7 +520,7 @@ struct LinearDomain {
           const float4 v = lds[t + k * nc];
           tot.x += v.x; tot.y += v.y; tot.z += v.z; tot.w += v.w;
         }
-        o4[col] = tot;
+        cst4(out + 4 * col, tot);
       }
       __syncthreads();
     }
@@ -567,8 +590,8 @@ struct XRangeDomain {
       __syncthreads();
       for (int i = threadIdx.x; i < kR; i += kBlock) {
         const bool ok = i < r;
-        lds[i] = ok ? gld(src + i) : kNegBig;
-        lds[kR + i] = ok ? gld(src + r + i) : 0.f;
+        lds[i] = ok ? cld(src + i) : kNegBig;
+        lds[kR + i] = ok ? cld(src + r + i) : 0.f;
       }
       __syncthreads();
       return;
@@ -579,8 +602,8 @@ struct XRangeDomain {
       const int col = 4 * cl + 4 * G * c;
       const bool ok = col < r;
       const int cc = ok ? col : 0;
-      const float4 e = gld4(src + cc);
-      const float4 m = gld4(src + r + cc);
+      const float4 e = cld4(src + cc);
+      const float4 m = cld4(src + r + cc);
       S.vecE[c] = ok ? e : f4fill(kNegBig);
       S.vecM[c] = ok ? m : f4zero();
     }
@@ -823,11 +846,11 @@ struct XRangeDomain {
         for (int w = 1; w < kWaves; ++w) s += lds[w * r + col];
         if (final) {
           float E, M;
-          frame_to_pair(s, frame[col], E, M);
-          out[col] = E;
-          out[r + col] = M;
+          frame_to_pair(s, cld(frame + col), E, M);
+          cst(out + col, E);
+          cst(out + r + col, M);
         } else {
-          out[col] = s;
+          cst(out + col, s);
         }
       }
       __syncthreads();
@@ -869,8 +892,8 @@ struct XRangeDomain {
 #pragma unroll
       for (int w = 1; w < kWaves; ++w)
         xr_combine(e, m, lds[(2 * w) * r + col], lds[(2 * w + 1) * r + col]);
-      out[col] = e;
-      out[r + col] = m;
+      cst(out + col, e);
+      cst(out + r + col, m);
     }
     __syncthreads();
   }
@@ -896,11 +919,11 @@ struct XRangeDomain {
       float e = kNegBig, m = 0.f;
       if (split < Sn) {
         for (int b = split; b < g; b += Sn) {
-          const float* p = slots + (int64_t)members[b] * slot_stride;
+          const float* p = slots + (int64_t)cld(members + b) * slot_stride;
           if (FRAMED) {
-            m += p[col];
+            m += cld(p + col);
           } else {
-            xr_combine(e, m, p[col], p[r + col]);
+            xr_combine(e, m, cld(p + col), cld(p + r + col));
           }
         }
       }
@@ -917,7 +940,7 @@ struct XRangeDomain {
           }
         }
         if (FRAMED) {
-          frame_to_pair(tm, frame[col], te, tm);
+          frame_to_pair(tm, cld(frame + col), te, tm);
         } else if (tm > 0.f) {  // normalise the mantissa to [0.5, 1)
           int ex = 0;
           tm = frexpf(tm, &ex);
@@ -925,8 +948,8 @@ struct XRangeDomain {
         } else {
           te = kNegBig;
         }
-        out[col] = te;
-        out[r + col] = tm;
+        cst(out + col, te);
+        cst(out + r + col, tm);
       }
       __syncthreads();
     }
@@ -968,8 +991,8 @@ __device__ __forceinline__ bool finish_half_step(
     }
   }
   if (threadIdx.x == 0) {
-    D.dpart[br] = e_blk;
-    D.dpart[g + br] = b_blk;
+    cst(D.dpart + br, e_blk);
+    cst(D.dpart + g + br, b_blk);
   }
   if (!group_barrier(B)) return false;
   if (g > 1) {
@@ -1025,7 +1048,7 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
   double err = 0.0;
   int bad = 0;
   bool ok = true;
-  if (threadIdx.x == 0) D.members[br] = (int32_t)blockIdx.x;
+  if (threadIdx.x == 0) cst(D.members + br, (int32_t)blockIdx.x);
 
   // z^(0) = Prow^T u^(0), u^(0) = 1 or the caller's start.
   Dom::template zero<false>(S);
@@ -1125,7 +1148,7 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
     }
     if (copy && br == 0) {
       const float* wfin = wbuf(kf);
-      for (int c = threadIdx.x; c < r * Dom::kVecStride; c += kBlock) D.w[c] = wfin[c];
+      for (int c = threadIdx.x; c < r * Dom::kVecStride; c += kBlock) D.w[c] = cld(wfin + c);
     }
     for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
       double lu = Dom::log_scaling(D.u, i, D.n);
@@ -1134,7 +1157,7 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
     }
   }
   const double blk = block_dsum(part, sh.d);
-  if (threadIdx.x == 0) D.dpart[2 * g + br] = blk;
+  if (threadIdx.x == 0) cst(D.dpart + 2 * g + br, blk);
   if (!group_barrier(B)) {
     if (br == 0 && threadIdx.x == 0) D.info->status = SK_ETIMEOUT;
     return;
