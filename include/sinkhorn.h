@@ -234,6 +234,58 @@ int sinkhorn_divergence_batched(const sk_problem* problems, int32_t count,
                                 void* const* states, void* ws,
                                 size_t ws_bytes, sk_stream_t stream);
 
+/* One run of Algorithm 1 inside sinkhorn_solve_batched, on the factored
+ * kernel K = Prow Pcol^T (Sec. 3.1).  All pointers are device pointers:
+ *   Prow (n x r), Pcol (m x r)  features in the layout opts->range selects
+ *                               (as written by sinkhorn_features);
+ *   a (n), b (m)                positive weights (row and column marginals);
+ *   srow (n), scol (m)          row log-scales of Prow / Pcol, or NULL: when
+ *                               given, w_hat is reported for the unscaled
+ *                               features, eps(a^T log u + b^T log v) with
+ *                               u = u~ e^(-srow) (the row-scaling identity);
+ *   u (n), v (m), w (r), z (r)  scalings and r-vectors, 8 bytes per entry
+ *                               (pair layout [E | M] in the extended range,
+ *                               first half used in the linear one); u is
+ *                               read as the starting scaling when
+ *                               opts->warm_start is set; all four are
+ *                               written (w = Pcol^T v, z = Prow^T u);
+ *   info                        device record written at the end;
+ *   eps                         the regularisation, only scales w_hat. */
+typedef struct {
+  const float* Prow;
+  const float* Pcol;
+  const float* a;
+  const float* b;
+  const float* srow;
+  const float* scol;
+  float* u;
+  float* v;
+  float* w;
+  float* z;
+  sk_solve_info* info;
+  int64_t n, m, r;
+  double eps;
+} sk_solve_spec;
+
+/* Workspace bytes for sinkhorn_solve_batched on these specs (host); 0 if a
+ * spec is invalid. */
+size_t sinkhorn_solve_batched_workspace_size(const sk_solve_spec* specs,
+                                             int32_t count);
+
+/* `count` independent runs of Algorithm 1 (specs: HOST array) in persistent
+ * launches that pack solves of uneven size, one launch per feature-count
+ * class, each solve on its own group of workgroups.  With
+ * opts->warm_start, each solve continues from the scaling in its u buffer:
+ * running K iterations and then K' more from the returned u gives the
+ * iterates of K + K' iterations (up to rounding), which is how a serving
+ * loop advances live requests in epochs.  Buffers of different specs must
+ * not overlap, except that features, weights and log-scales may be shared.
+ * Errors: SK_EINVAL (null pointer, n, m, r < 1, eps <= 0, count < 1, bad
+ * opts), SK_ENOTSUP (r > SK_MAX_R or r % 4 != 0), SK_ENOMEM (workspace). */
+int sinkhorn_solve_batched(const sk_solve_spec* specs, int32_t count,
+                           const sk_solve_opts* opts, void* ws,
+                           size_t ws_bytes, sk_stream_t stream);
+
 /* ------------------------------------------------------------------ (a8) */
 /* Adjoint of the feature map for the envelope gradient (Prop. 3.2 and the
  * point-location gradient of Sec. 3.3).  For one side of one solve with

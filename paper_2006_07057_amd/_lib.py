@@ -38,6 +38,13 @@ class sk_problem(ctypes.Structure):
                 ("r", c_i64), ("eps", ctypes.c_double), ("q", ctypes.c_double)]
 
 
+class sk_solve_spec(ctypes.Structure):
+    _fields_ = [("Prow", c_void), ("Pcol", c_void), ("a", c_void), ("b", c_void),
+                ("srow", c_void), ("scol", c_void), ("u", c_void), ("v", c_void),
+                ("w", c_void), ("z", c_void), ("info", c_void), ("n", c_i64),
+                ("m", c_i64), ("r", c_i64), ("eps", ctypes.c_double)]
+
+
 class sk_state_layout(ctypes.Structure):
     _fields_ = [("phix", c_size), ("phiy", c_size), ("sx", c_size),
                 ("sy", c_size), ("u", c_size * 3), ("v", c_size * 3),
@@ -68,6 +75,11 @@ SIGNATURES = {
                                             ctypes.POINTER(sk_solve_opts),
                                             c_void, ctypes.POINTER(c_void),
                                             c_void, c_size, c_void]),
+    "sinkhorn_solve_batched_workspace_size": (c_size, [ctypes.POINTER(sk_solve_spec),
+                                                       c_i32]),
+    "sinkhorn_solve_batched": (c_i32, [ctypes.POINTER(sk_solve_spec), c_i32,
+                                       ctypes.POINTER(sk_solve_opts), c_void,
+                                       c_size, c_void]),
     "sinkhorn_features_backward": (c_i32, [c_void, c_i64, c_i64, c_void, c_i64,
                                            c_void, c_void, c_void,
                                            ctypes.c_float, c_i32, c_i32, c_void,

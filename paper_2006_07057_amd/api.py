@@ -22,8 +22,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (lib, check, sk_problem, sk_solve_opts, sk_state_layout,
-                   SK_RANGE_EXTENDED, SK_RANGE_LINEAR)
+from ._lib import (lib, check, sk_problem, sk_solve_opts, sk_solve_spec,
+                   sk_state_layout, SK_RANGE_EXTENDED, SK_RANGE_LINEAR)
 
 EXTENDED, LINEAR = SK_RANGE_EXTENDED, SK_RANGE_LINEAR
 
@@ -334,6 +334,45 @@ def divergence_batched(problems: Sequence[tuple], tol=1e-6, max_iter=2000,
     for s in states:
         s.workspace = workspace
     return out, states
+
+
+def solve_spec(Prow, Pcol, a, b, u, v, w, z, info, eps=1.0, srow=None,
+               scol=None) -> sk_solve_spec:
+    """Descriptor of one solve for solve_batched (pointers of the given
+    device tensors; keep the tensors alive while the launch runs).  u, v, w,
+    z hold 8 bytes per entry; info holds one 24-byte record."""
+    n, r = Prow.shape
+    m = Pcol.shape[0]
+    return sk_solve_spec(Prow.data_ptr(), Pcol.data_ptr(), a.data_ptr(),
+                         b.data_ptr(), srow.data_ptr() if srow is not None else 0,
+                         scol.data_ptr() if scol is not None else 0,
+                         u.data_ptr(), v.data_ptr(), w.data_ptr(), z.data_ptr(),
+                         info.data_ptr(), n, m, r, float(eps))
+
+
+def solve_batched_workspace_bytes(specs: Sequence[sk_solve_spec]) -> int:
+    arr = (sk_solve_spec * len(specs))(*specs)
+    return int(lib().sinkhorn_solve_batched_workspace_size(arr, len(specs)))
+
+
+def solve_batched(specs: Sequence[sk_solve_spec], tol=1e-6, max_iter=2000,
+                  fixed_iter=0, warm_start=False, range=EXTENDED,
+                  workspace: Optional[torch.Tensor] = None, device=None):
+    """Run many solves in packed persistent launches (asynchronous).
+    Returns the workspace tensor used (reuse it for the next call)."""
+    count = len(specs)
+    arr = (sk_solve_spec * count)(*specs)
+    need = int(lib().sinkhorn_solve_batched_workspace_size(arr, count))
+    if need == 0:
+        raise ValueError("invalid solve specs")
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    o = _opts(tol, max_iter, fixed_iter, warm_start, range)
+    check(lib().sinkhorn_solve_batched(arr, count, ctypes.byref(o),
+                                       _ptr(workspace), workspace.numel(),
+                                       _stream(dev)), "sinkhorn_solve_batched")
+    return workspace
 
 
 # ------------------------------------------------------- instrumentation

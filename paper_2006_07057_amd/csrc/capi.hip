@@ -321,6 +321,27 @@ void divergence_specs(const sk_problem* p, void* state,
 
 constexpr size_t kBackwardScratchDoubles = 4096;
 
+int specs_from(const sk_solve_spec* in, int32_t count,
+               std::vector<SolveSpec>* out) {
+  if (!in || count < 1) return SK_EINVAL;
+  for (int32_t i = 0; i < count; ++i) {
+    const sk_solve_spec& p = in[i];
+    if (!p.Prow || !p.Pcol || !p.a || !p.b || !p.u || !p.v || !p.w || !p.z ||
+        !p.info)
+      return SK_EINVAL;
+    if (p.n < 1 || p.m < 1 || p.r < 1) return SK_EINVAL;
+    if (!(p.eps > 0.0) || !isfinite(p.eps)) return SK_EINVAL;
+    if (p.r > SK_MAX_R || p.r % 4 != 0) return SK_ENOTSUP;
+    SolveSpec sp;
+    sp.Prow = p.Prow; sp.Pcol = p.Pcol; sp.a = p.a; sp.b = p.b;
+    sp.srow = p.srow; sp.scol = p.scol;
+    sp.u = p.u; sp.v = p.v; sp.w = p.w; sp.z = p.z; sp.info = p.info;
+    sp.n = p.n; sp.m = p.m; sp.r = (int)p.r; sp.eps = p.eps;
+    out->push_back(sp);
+  }
+  return SK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -398,6 +419,30 @@ int sinkhorn_solve(const float* Phix, int64_t n, const float* Phiy, int64_t m,
   std::vector<SolveSpec> specs{sp};
   size_t need = 0;
   return run_solves(specs, opts, ws, ws_bytes, &need, S(stream));
+}
+
+size_t sinkhorn_solve_batched_workspace_size(const sk_solve_spec* specs,
+                                             int32_t count) {
+  std::vector<SolveSpec> v;
+  if (specs_from(specs, count, &v) != SK_OK) return 0;
+  size_t need = 0;
+  sk_solve_opts o{};
+  o.max_iter = 1;
+  run_solves(v, &o, nullptr, 0, &need, nullptr);
+  return need;
+}
+
+int sinkhorn_solve_batched(const sk_solve_spec* specs, int32_t count,
+                           const sk_solve_opts* opts, void* ws,
+                           size_t ws_bytes, sk_stream_t stream) {
+  std::vector<SolveSpec> v;
+  int rc = specs_from(specs, count, &v);
+  if (rc) return rc;
+  rc = check_opts(opts);
+  if (rc) return rc;
+  if (!ws) return SK_EINVAL;
+  size_t need = 0;
+  return run_solves(v, opts, ws, ws_bytes, &need, S(stream));
 }
 
 int sinkhorn_state_layout(int64_t n, int64_t m, int64_t r,
