@@ -316,6 +316,22 @@ int sinkhorn_divergence_backward(const sk_problem* p, const void* state,
                                  float* dY, float* db, void* ws,
                                  size_t ws_bytes, sk_stream_t stream);
 
+/* ------------------------------------------------------------ tuning (a6) */
+/* Per-process launch-planning table used by every solve of the feature
+ * count class that serves r (classes: 4, 8, 16, ..., 4096).  A solve of
+ * shape (n, m, r) runs on g = ceil(max(n, m) r 4 / target) workgroups
+ * (capped by the device's co-resident grid), so `target_bytes` is the
+ * feature bytes each workgroup streams per half-step: smaller targets mean
+ * more workgroups (more bandwidth, costlier barriers, fewer rows summed per
+ * lane).  target_bytes = 0 restores the built-in default (256 KiB).
+ * Written by the autotuner (host-only, not thread-safe against concurrent
+ * launches).  Errors: SK_EINVAL (r outside 1..SK_MAX_R, target < 0). */
+int sinkhorn_tune_set(int64_t r, int64_t target_bytes);
+
+/* Current target of the class serving r (the default if none was set), or
+ * a negative value for an invalid r. */
+int64_t sinkhorn_tune_get(int64_t r);
+
 /* ------------------------------------------------------- instrumentation */
 /* Launch timing for measurement: with enable != 0, every later launch of
  * the solver (kind 0), feature (kind 1) and adjoint (kind 2) kernels is

@@ -88,6 +88,8 @@ SIGNATURES = {
                                              c_void, c_void, c_void, c_void,
                                              c_void, c_void, c_void, c_size,
                                              c_void]),
+    "sinkhorn_tune_set": (c_i32, [c_i64, c_i64]),
+    "sinkhorn_tune_get": (c_i64, [c_i64]),
     "sinkhorn_profile": (c_i32, [c_i32]),
     "sinkhorn_profile_read": (c_i32, [c_i32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(c_i64),

@@ -375,6 +375,19 @@ def solve_batched(specs: Sequence[sk_solve_spec], tol=1e-6, max_iter=2000,
     return workspace
 
 
+def tune_set(r: int, target_bytes: int):
+    """Set the feature bytes per workgroup for the solver class serving r
+    (0 restores the default)."""
+    check(lib().sinkhorn_tune_set(int(r), int(target_bytes)), "sinkhorn_tune_set")
+
+
+def tune_get(r: int) -> int:
+    v = int(lib().sinkhorn_tune_get(int(r)))
+    if v < 0:
+        raise ValueError(f"no solver class for r={r}")
+    return v
+
+
 # ------------------------------------------------------- instrumentation
 PROF_SOLVER, PROF_FEATURES, PROF_ADJOINT = 0, 1, 2
 

@@ -72,9 +72,11 @@ std::map<int, int64_t>& tuning_table() {
 
 int class_rmax(int r) { return solver_class_rmax(r); }
 
+constexpr int64_t kDefaultTarget = 256 * 1024;
+
 int planned_group(int64_t n, int64_t m, int r) {
   const int cls = class_rmax(r);
-  int64_t target = 256 * 1024;
+  int64_t target = kDefaultTarget;
   auto it = tuning_table().find(cls);
   if (it != tuning_table().end() && it->second > 0) target = it->second;
   const int64_t rows = n > m ? n : m;
@@ -156,6 +158,25 @@ int run_solves(const std::vector<SolveSpec>& specs, const sk_solve_opts* o,
       return wx > wy;
     });
     const ClassBufs& cb = bufs[rmax];
+    // A solve starts once all of its g seats are taken, so workgroups that
+    // take seats of a solve whose other seats are still held elsewhere wait.
+    // The three solves of one divergence run one after the other on the
+    // whole grid (their iteration counts differ, and a finished solve's
+    // workgroups cannot join another).  A launch packing more solves gives
+    // each a share of the grid proportional to its work per iteration, so
+    // the gangs run side by side instead of queueing for the full grid.
+    std::vector<int> gshare(specs.size());
+    if (order.size() > 3) {
+      double total = 0.0;
+      for (int i : order) total += (double)(specs[i].n + specs[i].m) * specs[i].r;
+      for (int i : order) {
+        const double w = (double)(specs[i].n + specs[i].m) * specs[i].r;
+        const int64_t gi = (int64_t)((double)capdev * w / total);
+        gshare[i] = (int)std::max<int64_t>(1, std::min<int64_t>(gi, gplan[i]));
+      }
+    } else {
+      for (int i : order) gshare[i] = gplan[i];
+    }
     std::vector<SolveDesc> descs(order.size());
     int seat = 0;
     int64_t moff = 0;
@@ -176,7 +197,7 @@ int run_solves(const std::vector<SolveSpec>& specs, const sk_solve_opts* o,
       D.tol = o->tol;
       D.eps = sp.eps;
       D.n = sp.n; D.m = sp.m; D.r = sp.r;
-      D.g = std::min(gplan[i], capdev);
+      D.g = std::min(gshare[i], capdev);
       D.max_iter = o->max_iter;
       D.fixed_iter = o->fixed_iter;
       D.warm = o->warm_start;
@@ -443,6 +464,23 @@ int sinkhorn_solve_batched(const sk_solve_spec* specs, int32_t count,
   if (!ws) return SK_EINVAL;
   size_t need = 0;
   return run_solves(v, opts, ws, ws_bytes, &need, S(stream));
+}
+
+int sinkhorn_tune_set(int64_t r, int64_t target_bytes) {
+  if (r < 1 || r > SK_MAX_R || target_bytes < 0) return SK_EINVAL;
+  const int cls = class_rmax((int)r);
+  if (cls <= 0) return SK_EINVAL;
+  if (target_bytes == 0) tuning_table().erase(cls);
+  else tuning_table()[cls] = target_bytes;
+  return SK_OK;
+}
+
+int64_t sinkhorn_tune_get(int64_t r) {
+  if (r < 1 || r > SK_MAX_R) return -1;
+  const int cls = class_rmax((int)r);
+  if (cls <= 0) return -1;
+  auto it = tuning_table().find(cls);
+  return it != tuning_table().end() ? it->second : kDefaultTarget;
 }
 
 int sinkhorn_state_layout(int64_t n, int64_t m, int64_t r,

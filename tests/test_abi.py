@@ -18,7 +18,7 @@ HEADER = os.path.join(ROOT, "include", "sinkhorn.h")
 
 def _declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+"
+    return sorted(set(re.findall(r"^\s*(?:int64_t|int|size_t|const char\*)\s+"
                                  r"(sinkhorn_\w+)\s*\(", text, re.M)))
 
 

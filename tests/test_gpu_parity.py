@@ -347,9 +347,11 @@ def test_divergence_multi_workgroup_groups(api, rng_mode):
 
 @pytest.mark.parametrize("rng_mode", RANGES)
 def test_batched_equals_single(api, rng_mode):
-    """Several uneven problems in one batched call give the same results as
-    each problem alone (each solve's arithmetic does not depend on what
-    else shares the launch)."""
+    """Several uneven problems in one batched call give the results of each
+    problem alone.  A launch that packs more than three solves sizes their
+    workgroup gangs by work share, so each solve's rows are split over a
+    different number of workgroups than alone: equal up to float32 rounding
+    of the partial sums (and of the stop test near the tolerance)."""
     _say("batched vs single", rng_mode)
     probs = []
     rng = np.random.default_rng(5)
@@ -369,8 +371,9 @@ def test_batched_equals_single(api, rng_mode):
     for i, P in enumerate(probs):
         o1, s1 = api.divergence(*P, tol=1e-6, max_iter=3000, range=rng_mode)
         o1 = host(o1)
-        np.testing.assert_array_equal(ob[i], o1)
-        np.testing.assert_array_equal(sts[i].infos()["iters"], s1.infos()["iters"])
+        np.testing.assert_allclose(ob[i], o1, rtol=1e-6, atol=1e-9)
+        for ib, i1 in zip(sts[i].infos()["iters"], s1.infos()["iters"]):
+            assert abs(int(ib) - int(i1)) <= max(3, 0.05 * int(i1)), (i, ib, i1)
 
 
 @pytest.mark.parametrize("rng_mode", RANGES)
