@@ -305,6 +305,80 @@ def features_backward(X, U, Phi, p, g, coef=1.0, dX=None, accumulate=False,
 
 
 # ------------------------------------------------------------------ (a6)
+class DivergenceGraph:
+    """One divergence step (features, the three solves, the float64
+    assembly and optionally the adjoint) captured once as a HIP graph and
+    replayed, for repeated calls on fixed shapes (an optimisation loop over
+    point locations, a fixed-shape serving batch).  Every launch of the step
+    is a library kernel; none of them allocates, copies or sets memory, so
+    the captured graph is exactly the eager sequence.  Inputs are copied
+    into the graph's static buffers before each replay; results are the
+    static output tensors (overwritten by the next replay)."""
+
+    def __init__(self, n, m, d, r, eps, q, tol=1e-6, max_iter=2000, fixed_iter=0,
+                 range=EXTENDED, backward=True, device="cuda:0"):
+        dev = torch.device(device)
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.X = torch.zeros((n, d), **f32)
+        self.Y = torch.zeros((m, d), **f32)
+        self.a = torch.full((n,), 1.0 / n, **f32)
+        self.b = torch.full((m,), 1.0 / m, **f32)
+        self.U = torch.zeros((r, d), **f32)
+        self.kw = dict(tol=tol, max_iter=max_iter, fixed_iter=fixed_iter, range=range)
+        self.eps, self.q, self.backward = float(eps), float(q), bool(backward)
+        self.state = DivergenceState(self.X, self.Y, self.a, self.b, self.U, eps, q)
+        self.state.range = int(range)
+        need = max(divergence_workspace_bytes(self.state), 32768)
+        self.workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.out = torch.empty(4, dtype=torch.float64, device=dev)
+        self.grads = tuple(torch.empty_like(t) for t in (self.X, self.a, self.Y, self.b))
+        self.graph = None
+
+    def _step(self, stream):
+        o = _opts(self.kw["tol"], self.kw["max_iter"], self.kw["fixed_iter"], False,
+                  self.kw["range"])
+        st = self.state
+        check(lib().sinkhorn_divergence(ctypes.byref(st.problem), ctypes.byref(o),
+                                        _ptr(self.out), _ptr(st.buf), st.buf.numel(),
+                                        _ptr(self.workspace), self.workspace.numel(),
+                                        stream), "sinkhorn_divergence")
+        if self.backward:
+            dX, da, dY, db = self.grads
+            check(lib().sinkhorn_divergence_backward(
+                ctypes.byref(st.problem), _ptr(st.buf), _ptr(None), _ptr(dX), _ptr(da),
+                _ptr(dY), _ptr(db), _ptr(self.workspace), self.workspace.numel(), stream),
+                "sinkhorn_divergence_backward")
+
+    def capture(self):
+        dev = self.X.device
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):  # one eager run before capture
+            self._step(_stream(dev))
+        torch.cuda.current_stream(dev).wait_stream(side)
+        torch.cuda.synchronize(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._step(_stream(dev))
+        return self
+
+    def __call__(self, X, Y, a=None, b=None, U=None):
+        """Copy the inputs in and replay (asynchronous).  Returns
+        (out [W_bar, W_xy, W_xx, W_yy], (dX, da, dY, db) or None)."""
+        if self.graph is None:
+            self.capture()
+        self.X.copy_(X)
+        self.Y.copy_(Y)
+        if a is not None:
+            self.a.copy_(a)
+        if b is not None:
+            self.b.copy_(b)
+        if U is not None:
+            self.U.copy_(U)
+        self.graph.replay()
+        return self.out, (self.grads if self.backward else None)
+
+
 def divergence_batched(problems: Sequence[tuple], tol=1e-6, max_iter=2000,
                        fixed_iter=0, range=EXTENDED,
                        workspace: Optional[torch.Tensor] = None):

@@ -1,0 +1,118 @@
+"""HIP-graph capture of a divergence step, and the launch-planning
+autotuner.  CPU tests cover the tuning table's storage; GPU tests replay the
+captured graph against eager runs and check that tuning changes timing, not
+results."""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_07057_amd import autotune, inputs
+
+
+def test_class_of():
+    assert autotune.class_of(1) == 4
+    assert autotune.class_of(128) == 128
+    assert autotune.class_of(129) == 256
+    assert autotune.class_of(4096) == 4096
+    with pytest.raises(ValueError):
+        autotune.class_of(4097)
+
+
+def test_table_save_load_roundtrip(tmp_path):
+    from paper_2006_07057_amd import api
+    autotune.reset()
+    default = api.tune_get(256)
+    table = {256: 512 << 10, 1024: 4 << 20}
+    p = str(tmp_path / "tune.json")
+    with open(p, "w") as f:
+        json.dump({"device": None, "targets": {str(k): v for k, v in table.items()}}, f)
+    assert autotune.load(p) == table
+    assert api.tune_get(200) == 512 << 10      # same class as 256
+    assert api.tune_get(1000) == 4 << 20
+    assert api.tune_get(64) == default
+    autotune.save(str(tmp_path / "again.json"))
+    back = json.load(open(tmp_path / "again.json"))["targets"]
+    assert int(back["256"]) == 512 << 10 and int(back["64"]) == default
+    autotune.reset()
+    assert api.tune_get(256) == default
+
+
+def test_table_rejects_bad_entries(tmp_path):
+    from paper_2006_07057_amd import api
+    p = str(tmp_path / "bad.json")
+    with open(p, "w") as f:
+        json.dump({"targets": {"100": 1024}}, f)   # not a class
+    with pytest.raises(ValueError):
+        autotune.load(p)
+    with pytest.raises(Exception):
+        api.tune_set(5000, 1024)
+    with pytest.raises(Exception):
+        api.tune_set(64, -1)
+
+
+# ------------------------------------------------------------------- GPU
+def _inputs(seed, n, m, d, r):
+    c = inputs.gauss2d(seed, n=n, m=m, d=d)
+    U = inputs.gaussian_anchors(0, r, d, 1.0)   # same anchors for every call
+    return c.X, c.Y, c.a, c.b, U
+
+
+@pytest.mark.gpu
+def test_graph_replays_match_eager():
+    import torch
+    from paper_2006_07057_amd import api
+    n, m, d, r, eps = 2000, 1500, 3, 128, 0.5
+    q = 4.0 / eps
+    G = api.DivergenceGraph(n, m, d, r, eps, q, tol=1e-6, max_iter=2000)
+    t = lambda x: torch.from_numpy(x).cuda()
+    noise = torch.randn(512, 512, device="cuda")
+    for rep in range(4):
+        X, Y, a, b, U = (t(x) for x in _inputs(10 + rep, n, m, d, r))
+        out_g, grads_g = G(X, Y, a, b, U)
+        out_g = out_g.cpu().numpy().copy()
+        grads_g = [g.cpu().numpy().copy() for g in grads_g]
+        # eager work and synchronisation between replays
+        for _ in range(3):
+            noise = torch.tanh(noise @ noise.T)
+        torch.cuda.synchronize()
+        out_e, st = api.divergence(X, Y, a, b, U, eps, q, tol=1e-6, max_iter=2000)
+        grads_e = api.divergence_backward(st)
+        np.testing.assert_array_equal(out_g, out_e.cpu().numpy())
+        for g1, g2 in zip(grads_g, grads_e):
+            np.testing.assert_array_equal(g1, g2.cpu().numpy())
+
+
+@pytest.mark.gpu
+def test_graph_matches_oracle():
+    import torch
+    from paper_2006_07057_amd import api
+    n, m, d, r, eps = 400, 300, 2, 64, 0.5
+    q = 4.0 / eps
+    X, Y, a, b, U = _inputs(3, n, m, d, r)
+    G = api.DivergenceGraph(n, m, d, r, eps, q, fixed_iter=150, backward=False)
+    t = lambda x: torch.from_numpy(x).cuda()
+    out, _ = G(t(X), t(Y), t(a), t(b), t(U))
+    ref = oracle.divergence_scaled(X, Y, a, b, U, eps, q, fixed_iter=150)
+    assert float(out[0].item()) == pytest.approx(ref.value, rel=1e-5)
+
+
+@pytest.mark.gpu
+def test_autotune_changes_timing_not_results():
+    import torch
+    from paper_2006_07057_amd import api
+    autotune.reset()
+    n, r = 40000, 128
+    Px, Py, a, b = autotune._problem(n, n, r, 3, 0.5, 0, api.EXTENDED, torch.device("cuda"))
+    ref = api.solve(Px, Py, a, b, fixed_iter=30)
+    ref_u = api.host_log_scaling(ref.u, api.EXTENDED)
+    times = autotune.tune_class(r, n, candidates=(64 << 10, 256 << 10, 4 << 20), iters=10)
+    assert set(times) == {64 << 10, 256 << 10, 4 << 20}
+    assert all(t > 0 for t in times.values())
+    assert api.tune_get(r) == min(times, key=times.get)
+    got = api.solve(Px, Py, a, b, fixed_iter=30)
+    got_u = api.host_log_scaling(got.u, api.EXTENDED)
+    np.testing.assert_allclose(got_u, ref_u, rtol=0, atol=2e-5)
+    assert got.info()["w_hat"] == pytest.approx(ref.info()["w_hat"], rel=1e-6)
+    autotune.reset()
