@@ -180,6 +180,142 @@ features_kernel(const FeatDesc* __restrict__ descs, int count, FeatDesc one,
   }
 }
 
+// ------------------------------------------------------------ MFMA path
+// For large d the squared distance is expanded:
+//   E_ik = c_k + (4/eps) x_i.u_k - (2/eps)||x_i||^2,
+//   c_k  = -log(r)/2 + (d/4) log(2q) + (1/(eps q) - 2/eps)||u_k||^2.
+// The ||x_i||^2 term is the same for every k of a row, so it cancels in
+// E - s and only enters s; what remains, D_ik = c_k + (4/eps) x_i.u_k, is a
+// plain dot product (no cancellation), computed with fp32 matrix-core
+// instructions (16x16x4).  The norms are summed in float64 from the same
+// operand loads.  A workgroup owns 64 rows (16 per wave) across all r
+// columns: it writes D and tracks the row maxima column block by column
+// block, then normalises its rows in place.
+typedef float f4v __attribute__((ext_vector_type(4)));
+constexpr int kMfmaRows = 64;
+constexpr int kMfmaCols = 64;
+
+template <bool LOG2>
+__global__ void __launch_bounds__(kBlock)
+features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
+                     const float* __restrict__ U, int r, float c0, float cu,
+                     float scale, float neg2e, float* __restrict__ Phi,
+                     float* __restrict__ logscale) {
+  __shared__ float s_xn[kMfmaRows];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int q = lane >> 4;    // k slot of this lane (operands), row group (result)
+  const int l16 = lane & 15;  // row (operand A) / column (operand B, result)
+  const int64_t row_base = (int64_t)blockIdx.x * kMfmaRows + wave * 16;
+  const int64_t arow = row_base + l16;
+  const bool arow_ok = arow < n;
+  const float* xa = X + (arow_ok ? arow : 0) * (int64_t)d;
+  // lane group q covers k in [q kg, (q + 1) kg); kg is a multiple of 4
+  const int kg = ((d / 4 + 3) / 4) * 4;
+  const int k0 = q * kg;
+  float mrow[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  double xn = 0.0;
+  for (int cb = 0; cb < r; cb += kMfmaCols) {
+    f4v acc[4];
+    double un[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
+      un[t] = 0.0;
+    }
+    for (int s = 0; s < kg; s += 4) {
+      const int k = k0 + s;
+      const bool kok = k < d;  // d % 4 == 0, so k < d implies k + 3 < d
+      f4v a = f4v{0.f, 0.f, 0.f, 0.f};
+      if (kok && arow_ok) a = *reinterpret_cast<const f4v*>(xa + k);
+      if (cb == 0)
+        xn += (double)a.x * a.x + (double)a.y * a.y + (double)a.z * a.z +
+              (double)a.w * a.w;
+      f4v b[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int col = cb + 16 * t + l16;
+        b[t] = f4v{0.f, 0.f, 0.f, 0.f};
+        if (kok && col < r) b[t] = *reinterpret_cast<const f4v*>(U + (int64_t)col * d + k);
+        un[t] += (double)b[t].x * b[t].x + (double)b[t].y * b[t].y +
+                 (double)b[t].z * b[t].z + (double)b[t].w * b[t].w;
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[t][e], acc[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      un[t] += __shfl_xor(un[t], 16, 64);
+      un[t] += __shfl_xor(un[t], 32, 64);
+    }
+    // lane holds acc[t][v] = x_{row_base + 4q + v} . u_{cb + 16t + l16}
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int col = cb + 16 * t + l16;
+      if (col >= r) continue;
+      const float cval = fmaf(cu, (float)un[t], c0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = row_base + 4 * q + v;
+        const float Dv = fmaf(scale, acc[t][v], cval);
+        mrow[v] = fmaxf(mrow[v], Dv);
+        if (row < n) Phi[row * (int64_t)r + col] = Dv;
+      }
+    }
+  }
+  xn += __shfl_xor(xn, 16, 64);
+  xn += __shfl_xor(xn, 32, 64);
+  if (q == 0) s_xn[wave * 16 + l16] = (float)xn;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) mrow[v] = group_max<16>(mrow[v]);
+  __syncthreads();
+  // normalise the rows this lane wrote (program order: its own stores)
+  for (int cb = 0; cb < r; cb += kMfmaCols) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int col = cb + 16 * t + l16;
+      if (col >= r) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = row_base + 4 * q + v;
+        if (row >= n) continue;
+        float* p = Phi + row * (int64_t)r + col;
+        const float x = *p - mrow[v];
+        *p = LOG2 ? x * kLog2e : expf(x);
+      }
+    }
+  }
+  if (l16 == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = row_base + 4 * q + v;
+      if (row < n) logscale[row] = fmaf(neg2e, s_xn[wave * 16 + 4 * q + v], mrow[v]);
+    }
+  }
+}
+
+bool use_mfma(int d) { return d >= 32 && d % 4 == 0; }
+
+hipError_t launch_mfma(const FeatDesc& D, hipStream_t s) {
+  const int64_t blocks = (D.n + kMfmaRows - 1) / kMfmaRows;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const double eps = D.eps, q = D.q;
+  const float c0 = (float)(-0.5 * log((double)D.r) + 0.25 * D.d * log(2.0 * q));
+  const float cu = (float)(1.0 / (eps * q) - 2.0 / eps);
+  const float scale = (float)(4.0 / eps);
+  const float neg2e = (float)(-2.0 / eps);
+  if (D.log2_out)
+    hipLaunchKernelGGL(features_mfma_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), 0,
+                       s, D.X, D.n, D.d, D.U, D.r, c0, cu, scale, neg2e, D.Phi, D.s);
+  else
+    hipLaunchKernelGGL(features_mfma_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), 0,
+                       s, D.X, D.n, D.d, D.U, D.r, c0, cu, scale, neg2e, D.Phi, D.s);
+  return hipGetLastError();
+}
+
 typedef void (*FeatLaunch)(dim3, hipStream_t, const FeatDesc*, int,
                            const FeatDesc&, int64_t);
 
@@ -255,10 +391,15 @@ hipError_t launch_features(const float* X, int64_t n, int d, const float* U,
   one.n = n; one.d = d; one.r = r;
   one.eps = (float)eps; one.q = (float)q; one.tile0 = 0;
   one.log2_out = log2_out;
-  const int64_t tiles = (n + cls->rows_per_tile - 1) / cls->rows_per_tile;
   void* tok = prof_begin(kProfFeatures, s);
-  cls->launch(dim3((unsigned)feature_grid(tiles)), s, nullptr, 1, one, tiles);
-  const hipError_t e = hipGetLastError();
+  hipError_t e;
+  if (use_mfma(d)) {
+    e = launch_mfma(one, s);
+  } else {
+    const int64_t tiles = (n + cls->rows_per_tile - 1) / cls->rows_per_tile;
+    cls->launch(dim3((unsigned)feature_grid(tiles)), s, nullptr, 1, one, tiles);
+    e = hipGetLastError();
+  }
   prof_end(tok, s);
   return e;
 }
@@ -269,12 +410,30 @@ hipError_t launch_features_batched(const FeatDesc* host, int count,
   // All problems of one call share the feature class; the caller groups.
   const FeatClass* cls = feat_class(host[0].r);
   if (!cls) return hipErrorInvalidValue;
+  // problems with large d take the matrix-core path, one launch each
   FeatDesc* tmp = new FeatDesc[count];
+  int nv = 0;
   int64_t tiles = 0;
   for (int i = 0; i < count; ++i) {
-    tmp[i] = host[i];
-    tmp[i].tile0 = tiles;
+    if (use_mfma(host[i].d)) {
+      void* tk = prof_begin(kProfFeatures, s);
+      const hipError_t em = launch_mfma(host[i], s);
+      prof_end(tk, s);
+      if (em != hipSuccess) {
+        delete[] tmp;
+        return em;
+      }
+      continue;
+    }
+    tmp[nv] = host[i];
+    tmp[nv].tile0 = tiles;
     tiles += (host[i].n + cls->rows_per_tile - 1) / cls->rows_per_tile;
+    ++nv;
+  }
+  count = nv;
+  if (count == 0) {
+    delete[] tmp;
+    return hipSuccess;
   }
   // descriptors go up with stream-ordered kernels (graph capturable)
   hipError_t e = upload_bytes(dev_scratch, tmp, sizeof(FeatDesc) * (size_t)count, s);

@@ -59,6 +59,14 @@ def _feature_tol(X, U, eps, q):
     E = oracle.gaussian_log_features(X, U, eps, q)
     c = np.abs(E + (2.0 / eps) * d2)
     mag = (2.0 / eps) * d2 * (d + 3) + c + np.abs(E)
+    if d >= 32 and d % 4 == 0:
+        # matrix-core path: E - s is formed from c_k + (4/eps) x.u with the
+        # dot product accumulated over d float32 terms, and s adds the
+        # float32 product (2/eps)||x||^2
+        dot = np.abs(X) @ np.abs(U).T
+        xn = (X ** 2).sum(1)[:, None]
+        un = (U ** 2).sum(1)[None, :]
+        mag = mag + (4.0 / eps) * dot * (d + 3) + (2.0 / eps) * (xn + un) + np.abs(c)
     return 8 * 2.0 ** -24 * (mag.max(1) + 1.0)
 
 
@@ -343,6 +351,27 @@ def test_divergence_multi_workgroup_groups(api, rng_mode):
                                    dense=False)
     _say("W_bar gpu", g[0], "oracle", ref.value)
     assert g[0] == pytest.approx(ref.value, rel=DIV_RTOL)
+
+
+@pytest.mark.parametrize("n,m,d,r,eps,kind", [
+    (300, 260, 784, 512, 10.0, "pixels"),    # pixel-like, matrix-core features
+    (400, 400, 128, 256, 1.0, "sphere"),     # unit-normalised Gaussian vectors
+])
+def test_large_d_divergence_matches_oracle(api, n, m, d, r, eps, kind):
+    """End to end through the matrix-core feature path (d >= 32)."""
+    _say("large-d divergence", kind, n, m, d, r)
+    if kind == "pixels":
+        c = inputs.pixels(3, n=n, m=m, d=d)
+    else:
+        c = inputs.sphere(3, n=n, m=m, d=d)
+    q = oracle.lambert_q(inputs.max_norm(c.X, c.Y), eps, d)
+    U = inputs.gaussian_anchors(3, r, d, oracle.sigma2_from_q(q, eps))
+    out, st = api.divergence(dev(c.X), dev(c.Y), dev(c.a), dev(c.b), dev(U), eps, q,
+                             fixed_iter=100)
+    ref = oracle.divergence_scaled(c.X, c.Y, c.a, c.b, U, eps, q, fixed_iter=100)
+    got = host(out)
+    assert got[0] == pytest.approx(ref.value, rel=DIV_RTOL, abs=1e-7 * abs(ref.w_xy))
+    assert got[1] == pytest.approx(ref.w_xy, rel=DIV_RTOL)
 
 
 @pytest.mark.parametrize("rng_mode", RANGES)
