@@ -188,12 +188,22 @@ features_kernel(const FeatDesc* __restrict__ descs, int count, FeatDesc one,
 // E - s and only enters s; what remains, D_ik = c_k + (4/eps) x_i.u_k, is a
 // plain dot product (no cancellation), computed with fp32 matrix-core
 // instructions (16x16x4).  The norms are summed in float64 from the same
-// operand loads.  A workgroup owns 64 rows (16 per wave) across all r
-// columns: it writes D and tracks the row maxima column block by column
-// block, then normalises its rows in place.
+// operands.
+//
+// A workgroup owns 64 rows (16 per wave) across all r columns, in column
+// blocks of 64 (four 16-wide tiles per wave).  Operands move in chunks of 32
+// k-values: coalesced global loads (8 lanes per 128-byte row segment) into
+// registers one chunk ahead, then into double-buffered LDS tiles padded to
+// 36 floats per row; each lane then reads 8 consecutive k of its row (lane
+// group q takes k in [8q, 8q + 8) of the chunk, an order the sum does not
+// depend on) as two 16-byte LDS reads.  Each column block writes D and
+// updates the row maxima; a final sweep over the workgroup's rows
+// normalises them in place.
 typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int kMfmaRows = 64;
 constexpr int kMfmaCols = 64;
+constexpr int kMfmaK = 32;
+constexpr int kMfmaPad = 36;  // floats per LDS row (bank spread)
 
 template <bool LOG2>
 __global__ void __launch_bounds__(kBlock)
@@ -201,20 +211,44 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
                      const float* __restrict__ U, int r, float c0, float cu,
                      float scale, float neg2e, float* __restrict__ Phi,
                      float* __restrict__ logscale) {
+  __shared__ float sA[2][kMfmaRows * kMfmaPad];
+  __shared__ float sB[2][kMfmaCols * kMfmaPad];
   __shared__ float s_xn[kMfmaRows];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int q = lane >> 4;    // k slot of this lane (operands), row group (result)
-  const int l16 = lane & 15;  // row (operand A) / column (operand B, result)
-  const int64_t row_base = (int64_t)blockIdx.x * kMfmaRows + wave * 16;
-  const int64_t arow = row_base + l16;
-  const bool arow_ok = arow < n;
-  const float* xa = X + (arow_ok ? arow : 0) * (int64_t)d;
-  // lane group q covers k in [q kg, (q + 1) kg); kg is a multiple of 4
-  const int kg = ((d / 4 + 3) / 4) * 4;
-  const int k0 = q * kg;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int q = lane >> 4;    // k group (operands) / row group (result)
+  const int l16 = lane & 15;  // row (A) / column (B and result)
+  const int64_t blk_row = (int64_t)blockIdx.x * kMfmaRows;
+  const int64_t row_base = blk_row + wave * 16;
+  // staging: thread t moves float4 (t % 8) of tile rows t / 8 and t / 8 + 32
+  const int st_f4 = tid & 7;
+  const int st_row = tid >> 3;
+  const int nchunks = (d + kMfmaK - 1) / kMfmaK;
   float mrow[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
   double xn = 0.0;
+
+  auto gload = [&](f4v (&ra)[2], f4v (&rb)[2], int cb, int kc) {
+    const int k = kc * kMfmaK + 4 * st_f4;
+    const bool kok = k < d;  // d % 4 == 0: k < d implies k + 3 < d
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t row = blk_row + st_row + 32 * h;
+      ra[h] = f4v{0.f, 0.f, 0.f, 0.f};
+      if (kok && row < n) ra[h] = *reinterpret_cast<const f4v*>(X + row * (int64_t)d + k);
+      const int col = cb + st_row + 32 * h;
+      rb[h] = f4v{0.f, 0.f, 0.f, 0.f};
+      if (kok && col < r) rb[h] = *reinterpret_cast<const f4v*>(U + (int64_t)col * d + k);
+    }
+  };
+  auto lstore = [&](int buf, const f4v (&ra)[2], const f4v (&rb)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      *reinterpret_cast<f4v*>(&sA[buf][(st_row + 32 * h) * kMfmaPad + 4 * st_f4]) = ra[h];
+      *reinterpret_cast<f4v*>(&sB[buf][(st_row + 32 * h) * kMfmaPad + 4 * st_f4]) = rb[h];
+    }
+  };
+
   for (int cb = 0; cb < r; cb += kMfmaCols) {
     f4v acc[4];
     double un[4];
@@ -223,28 +257,39 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
       acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
       un[t] = 0.0;
     }
-    for (int s = 0; s < kg; s += 4) {
-      const int k = k0 + s;
-      const bool kok = k < d;  // d % 4 == 0, so k < d implies k + 3 < d
-      f4v a = f4v{0.f, 0.f, 0.f, 0.f};
-      if (kok && arow_ok) a = *reinterpret_cast<const f4v*>(xa + k);
-      if (cb == 0)
-        xn += (double)a.x * a.x + (double)a.y * a.y + (double)a.z * a.z +
-              (double)a.w * a.w;
-      f4v b[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int col = cb + 16 * t + l16;
-        b[t] = f4v{0.f, 0.f, 0.f, 0.f};
-        if (kok && col < r) b[t] = *reinterpret_cast<const f4v*>(U + (int64_t)col * d + k);
-        un[t] += (double)b[t].x * b[t].x + (double)b[t].y * b[t].y +
-                 (double)b[t].z * b[t].z + (double)b[t].w * b[t].w;
+    f4v ra[2], rb[2];
+    gload(ra, rb, cb, 0);
+    __syncthreads();  // previous block's readers are done with buffer 0
+    lstore(0, ra, rb);
+    __syncthreads();
+    for (int kc = 0; kc < nchunks; ++kc) {
+      const int buf = kc & 1;
+      if (kc + 1 < nchunks) gload(ra, rb, cb, kc + 1);
+      const float* A = &sA[buf][(wave * 16 + l16) * kMfmaPad + 8 * q];
+      const f4v a0 = *reinterpret_cast<const f4v*>(A);
+      const f4v a1 = *reinterpret_cast<const f4v*>(A + 4);
+      if (cb == 0) {
+        xn += (double)a0.x * a0.x + (double)a0.y * a0.y + (double)a0.z * a0.z +
+              (double)a0.w * a0.w + (double)a1.x * a1.x + (double)a1.y * a1.y +
+              (double)a1.z * a1.z + (double)a1.w * a1.w;
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+      for (int t = 0; t < 4; ++t) {
+        const float* B = &sB[buf][(16 * t + l16) * kMfmaPad + 8 * q];
+        const f4v b0 = *reinterpret_cast<const f4v*>(B);
+        const f4v b1 = *reinterpret_cast<const f4v*>(B + 4);
+        un[t] += (double)b0.x * b0.x + (double)b0.y * b0.y + (double)b0.z * b0.z +
+                 (double)b0.w * b0.w + (double)b1.x * b1.x + (double)b1.y * b1.y +
+                 (double)b1.z * b1.z + (double)b1.w * b1.w;
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[t][e], acc[t], 0, 0, 0);
+        for (int e = 0; e < 4; ++e)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[e], b0[e], acc[t], 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[e], b1[e], acc[t], 0, 0, 0);
+      }
+      if (kc + 1 < nchunks) lstore(buf ^ 1, ra, rb);
+      __syncthreads();
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -272,7 +317,7 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
 #pragma unroll
   for (int v = 0; v < 4; ++v) mrow[v] = group_max<16>(mrow[v]);
   __syncthreads();
-  // normalise the rows this lane wrote (program order: its own stores)
+  // normalise the values this lane wrote (program order: its own stores)
   for (int cb = 0; cb < r; cb += kMfmaCols) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -297,7 +342,7 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
   }
 }
 
-bool use_mfma(int d) { return d >= 32 && d % 4 == 0; }
+bool use_mfma(int d) { return d >= 8 && d % 4 == 0; }
 
 hipError_t launch_mfma(const FeatDesc& D, hipStream_t s) {
   const int64_t blocks = (D.n + kMfmaRows - 1) / kMfmaRows;
