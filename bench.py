@@ -40,6 +40,10 @@ WORKLOADS = {
     # eps = 0.1, stop at L1 marginal error < 1e-6 or 2000 iterations
     "gmm3d_1m": dict(kind="gmm3d", n=1_000_000, m=1_000_000, d=3, r=1024,
                      eps=0.1, tol=1e-6, max_iter=2000, fixed_iter=0),
+    # pixel-like vectors U[0,1]^784, n = m = 65536, r = 4096, eps = 10,
+    # Lambert q: the matrix-core feature map dominates
+    "pixels_64k": dict(kind="pixels", n=65536, m=65536, d=784, r=4096, eps=10.0,
+                       tol=1e-6, max_iter=2000, fixed_iter=0),
     # x ~ N(0, I_2), y ~ N(1.5*1, I_2), n = m = 1000, r = 128, sigma^2 = 1,
     # 200 fixed iterations
     "gauss2d_1k": dict(kind="gauss2d", n=1000, m=1000, d=2, r=128, eps=0.5,
@@ -81,8 +85,9 @@ def plain_sinkhorn(torch, api, X, Y, a, b, U, wl, q, reps=5):
 
 
 def make_inputs(wl, seed, api, inputs):
-    if wl["kind"] == "gmm3d":
-        c = inputs.gmm3d(seed, n=wl["n"], m=wl["m"], d=wl["d"])
+    if wl["kind"] in ("gmm3d", "pixels"):
+        gen = inputs.gmm3d if wl["kind"] == "gmm3d" else inputs.pixels
+        c = gen(seed, n=wl["n"], m=wl["m"], d=wl["d"])
         R = inputs.max_norm(c.X, c.Y)
         q = api.gaussian_q(R, wl["eps"], wl["d"])
         sigma2 = q * wl["eps"] / 4.0
@@ -174,6 +179,47 @@ def copy_calibration(torch, gib):
     return 0
 
 
+MFMA_FP32_PEAK_TFLOPS = 157.3
+
+
+def run_features_only(args, wl, torch, api, X, Y, U, q):
+    """Feature map of both clouds (2 d r (n + m) flops of distance
+    contraction); for d >= 8 it runs on fp32 matrix cores."""
+    for _ in range(args.warmup):
+        api.features(X, U, wl["eps"], q)
+        api.features(Y, U, wl["eps"], q)
+    torch.cuda.synchronize()
+    api.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        api.features(X, U, wl["eps"], q)
+        api.features(Y, U, wl["eps"], q)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    feat_ms, feat_n, _ = api.profile_read(api.PROF_FEATURES)
+    api.profile(False)
+    n, m, d, r = wl["n"], wl["m"], wl["d"], wl["r"]
+    flops_launch = 2.0 * d * r * (n + m) / 2.0  # per launch (one cloud each)
+    avg_s = feat_ms / max(feat_n, 1) / 1e3
+    tf = flops_launch / avg_s / 1e12
+    rec = {
+        "metric": "feature-map TFLOP/s (distance contraction)",
+        "value": 2.0 * d * r * (n + m) * args.steps / elapsed / 1e12,
+        "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m, "d": d, "r": r,
+                   "eps": wl["eps"], "q": q, "step": "features of X and Y"},
+        "roofline": {"bound": "mfma", "kernel": "features_mfma_kernel",
+                     "achieved": tf, "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tf / MFMA_FP32_PEAK_TFLOPS, "traffic": None,
+                     "algorithmic_flops_per_launch": flops_launch,
+                     "avg_launch_ms": avg_s * 1e3},
+    }
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def run_stream(args, torch, api, inputs):
     """Serving workload: a Poisson stream of uneven divergence requests
     (n, m log-uniform in [2^10, 2^17], d in {2, 3, 16, 64}, r in {64, 256,
@@ -262,6 +308,9 @@ def main(argv=None):
     ap.add_argument("--stream-count", type=int, default=2048)
     ap.add_argument("--stream-rate", type=float, default=500.0)
     ap.add_argument("--epoch-iters", type=int, default=50)
+    ap.add_argument("--features-only", action="store_true",
+                    help="time only the feature map of both clouds (matrix-core "
+                         "roofline for large d)")
     ap.add_argument("--graph", action="store_true",
                     help="replay the step as a captured HIP graph")
     ap.add_argument("--seed", type=int, default=0)
@@ -293,6 +342,8 @@ def main(argv=None):
     t = lambda x: torch.from_numpy(x).to(dev)
     X, Y, a, b, Ud = t(c.X), t(c.Y), t(c.a), t(c.b), t(U)
     kw = dict(tol=wl["tol"], max_iter=wl["max_iter"], fixed_iter=wl["fixed_iter"])
+    if args.features_only:
+        return run_features_only(args, wl, torch, api, X, Y, Ud, q)
 
     state = None
     ws = None
