@@ -25,6 +25,8 @@ Pins (tests/test_oracle_pins.py, run without a GPU):
                                Gaussian kernel, symmetry, permutation.
   * divergence_grad          - central finite differences; large-r limit
                                of the squared-Euclidean Sinkhorn gradient.
+  * divergence_grad_anchors  - central finite differences of the divergence
+                               with respect to every anchor coordinate.
 No function here is "parity unpinned".
 """
 from __future__ import annotations
@@ -37,7 +39,7 @@ import numpy as np
 from scipy.special import lambertw
 
 __all__ = [
-    "lambert_q", "sigma2_from_q", "q_from_sigma2",
+    "lambert_q", "sigma2_from_q", "q_from_sigma2", "divergence_grad_anchors",
     "gaussian_log_features", "gaussian_features", "gaussian_features_scaled",
     "gaussian_kernel", "rf_kernel",
     "SinkhornResult", "sinkhorn", "sinkhorn_dense", "sinkhorn_factored",
@@ -368,6 +370,51 @@ def divergence_grad(X, Y, a, b, U, eps: float, q: float, tol: float = 1e-13,
     da = da - da.mean()
     db = db - db.mean()
     return dX, da, dY, db, div
+
+
+def _grad_anchors_one_solve(Zr, Zc, U, eps, q, Pr, Pc, p, g):
+    """Gradient of W_hat of one solve with respect to the anchors.
+
+    With K_ij = sum_k phi_k(z_i) phi_k(z'_j) and, from the log-feature of
+    Lemma 1, d log phi_k(z) / d u_k = (4/eps)(z - u_k) + (2/(eps q)) u_k,
+    the envelope gradient dW/dK = -eps p g^T of Prop. 3.2 gives
+        dW/du_k = -eps [ (sum_j g_j phi_k(z'_j)) sum_i p_i phi_k(z_i) dlog phi_k(z_i)
+                        + (sum_i p_i phi_k(z_i)) sum_j g_j phi_k(z'_j) dlog phi_k(z'_j) ].
+    """
+    Zr = np.asarray(Zr, F64)
+    Zc = np.asarray(Zc, F64)
+    U = np.asarray(U, F64)
+    Wr = p[:, None] * Pr                          # p_i phi_k(z_i)
+    Wc = g[:, None] * Pc                          # g_j phi_k(z'_j)
+    zr = Wr.sum(0)
+    zc = Wc.sum(0)
+    dr = (4.0 / eps) * (Wr.T @ Zr - zr[:, None] * U) + (2.0 / (eps * q)) * zr[:, None] * U
+    dc = (4.0 / eps) * (Wc.T @ Zc - zc[:, None] * U) + (2.0 / (eps * q)) * zc[:, None] * U
+    return -eps * (zc[:, None] * dr + zr[:, None] * dc)
+
+
+def divergence_grad_anchors(X, Y, a, b, U, eps: float, q: float, tol: float = 1e-13,
+                            max_iter: int = 100000, fixed_iter: int = 0):
+    """Gradient of the divergence with respect to the anchors U (r x d),
+    with q held fixed: dW_bar/dU = G(xy) - (G(xx) + G(yy)) / 2, each G from
+    the envelope gradient of Prop. 3.2 through the feature map.
+    Returns (dU, Divergence)."""
+    Phx = gaussian_features(X, U, eps, q)
+    Phy = gaussian_features(Y, U, eps, q)
+    sx = gaussian_log_features(X, U, eps, q).max(1)
+    sy = gaussian_log_features(Y, U, eps, q).max(1)
+    kw = dict(tol=tol, max_iter=max_iter, fixed_iter=fixed_iter)
+    xy = sinkhorn_dense(Phx @ Phy.T, a, b, u0=np.exp(-sx), **kw)
+    xx = sinkhorn_dense(Phx @ Phx.T, a, a, u0=np.exp(-sx), **kw)
+    yy = sinkhorn_dense(Phy @ Phy.T, b, b, u0=np.exp(-sy), **kw)
+    wxy = w_hat(xy.u, xy.v, a, b, eps)
+    wxx = w_hat(xx.u, xx.v, a, a, eps)
+    wyy = w_hat(yy.u, yy.v, b, b, eps)
+    div = Divergence(wxy - 0.5 * (wxx + wyy), wxy, wxx, wyy, xy, xx, yy)
+    dU = (_grad_anchors_one_solve(X, Y, U, eps, q, Phx, Phy, xy.u, xy.v)
+          - 0.5 * (_grad_anchors_one_solve(X, X, U, eps, q, Phx, Phx, xx.u, xx.v)
+                   + _grad_anchors_one_solve(Y, Y, U, eps, q, Phy, Phy, yy.u, yy.v)))
+    return dU, div
 
 
 def grad_x_exact_kernel(X, Y, a, b, eps: float, tol: float = 1e-13,

@@ -352,6 +352,21 @@ def test_gradients_match_finite_differences():
     assert abs(da.sum()) < 1e-12 and abs(db.sum()) < 1e-12
 
 
+def test_anchor_gradient_matches_finite_differences():
+    """Gradient with respect to the anchors (q fixed): central differences
+    of the converged divergence in every anchor coordinate."""
+    X, Y, a, b, U, eps, q = _small_problem(14, 7, 6, r=5, eps=0.8)
+    kw = dict(tol=1e-14, max_iter=1000000)
+    dU, div = oracle.divergence_grad_anchors(X, Y, a, b, U, eps, q, **kw)
+    assert div.value == pytest.approx(oracle.divergence(X, Y, a, b, U, eps, q, **kw).value,
+                                      rel=1e-12)
+
+    def fU(Up):
+        return oracle.divergence(X, Y, a, b, Up, eps, q, **kw).value
+
+    np.testing.assert_allclose(dU, _fd(fU, U, 1e-5), rtol=1e-6, atol=1e-9)
+
+
 def test_point_gradient_large_r_limit():
     """As r grows K_theta -> exp(-||x-y||^2/eps) and the row-side feature
     gradient of W(mu,nu) tends to the squared-Euclidean Sinkhorn gradient
