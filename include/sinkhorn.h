@@ -316,6 +316,22 @@ int sinkhorn_divergence_backward(const sk_problem* p, const void* state,
                                  float* dY, float* db, void* ws,
                                  size_t ws_bytes, sk_stream_t stream);
 
+/* Gradient of the divergence computed by sinkhorn_divergence (same problem
+ * and state) with respect to the anchors U (r x d), q held fixed: from
+ * Prop. 3.2 (dW/dK = -eps u v^T) and the Lemma 1 log-feature,
+ * d log phi_k(z)/d u_k = (4/eps)(z - u_k) + (2/(eps q)) u_k, one solve gives
+ *   dW/du_k = -4 [ sum_i u_i phi_k(x_i) w_k x_i + sum_j v_j phi_k(y_j) z_k y_j ]
+ *             + 4 (2 - 1/q) z_k w_k u_k,
+ * combined as dW(x,y) - (dW(x,x) + dW(y,y)) / 2 and scaled by *grad_out (a
+ * device float, or 1 if NULL).  dU: device r x d floats (overwritten).
+ * ws: sinkhorn_divergence_backward_anchors_workspace_size bytes (partial
+ * sums; the reduction is deterministic).  Errors: SK_EINVAL, SK_ENOMEM. */
+size_t sinkhorn_divergence_backward_anchors_workspace_size(const sk_problem* p);
+int sinkhorn_divergence_backward_anchors(const sk_problem* p, const void* state,
+                                         const float* grad_out, float* dU,
+                                         void* ws, size_t ws_bytes,
+                                         sk_stream_t stream);
+
 /* ------------------------------------------------------------ tuning (a6) */
 /* Per-process launch-planning table used by every solve of the feature
  * count class that serves r (classes: 4, 8, 16, ..., 4096).  A solve of

@@ -88,6 +88,11 @@ SIGNATURES = {
                                              c_void, c_void, c_void, c_void,
                                              c_void, c_void, c_void, c_size,
                                              c_void]),
+    "sinkhorn_divergence_backward_anchors_workspace_size": (
+        c_size, [ctypes.POINTER(sk_problem)]),
+    "sinkhorn_divergence_backward_anchors": (c_i32, [ctypes.POINTER(sk_problem), c_void,
+                                                     c_void, c_void, c_void, c_size,
+                                                     c_void]),
     "sinkhorn_tune_set": (c_i32, [c_i64, c_i64]),
     "sinkhorn_tune_get": (c_i64, [c_i64]),
     "sinkhorn_profile": (c_i32, [c_i32]),

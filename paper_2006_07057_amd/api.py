@@ -289,6 +289,23 @@ def divergence_backward(state: DivergenceState,
     return dX, da, dY, db
 
 
+def divergence_backward_anchors(state: DivergenceState,
+                                grad_out: Optional[torch.Tensor] = None):
+    """Gradient dU (r x d) of the divergence held in `state` with respect to
+    the anchors (q fixed)."""
+    dev = state.X.device
+    dU = torch.empty_like(state.U)
+    need = int(lib().sinkhorn_divergence_backward_anchors_workspace_size(
+        ctypes.byref(state.problem)))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    if grad_out is not None:
+        grad_out = grad_out.detach().to(device=dev, dtype=torch.float32).reshape(1).contiguous()
+    check(lib().sinkhorn_divergence_backward_anchors(
+        ctypes.byref(state.problem), _ptr(state.buf), _ptr(grad_out), _ptr(dU), _ptr(ws),
+        ws.numel(), _stream(dev)), "sinkhorn_divergence_backward_anchors")
+    return dU
+
+
 def features_backward(X, U, Phi, p, g, coef=1.0, dX=None, accumulate=False,
                       range=EXTENDED):
     """dX (+)= coef * 4 p_i (x_i (Phi_i . g) - sum_k Phi_ik g_k u_k)."""
@@ -495,12 +512,14 @@ class _SinkhornDivergenceFn(torch.autograd.Function):
         need = (ctx.needs_input_grad[0], ctx.needs_input_grad[2],
                 ctx.needs_input_grad[1], ctx.needs_input_grad[3])
         dX, da, dY, db = divergence_backward(ctx.state, g, need)
-        return dX, dY, da, db, None, None, None, None, None, None, None
+        dU = divergence_backward_anchors(ctx.state, g) if ctx.needs_input_grad[4] else None
+        return dX, dY, da, db, dU, None, None, None, None, None, None
 
 
 def sinkhorn_divergence(X, Y, a, b, U, eps, q, tol=1e-6, max_iter=2000,
                         fixed_iter=0, range=EXTENDED):
     """Differentiable debiased Sinkhorn divergence (float64 scalar tensor);
-    gradients flow to X, Y, a and b through the library's adjoint kernels."""
+    gradients flow to X, Y, a, b and the anchors U (q held fixed) through the
+    library's adjoint kernels."""
     return _SinkhornDivergenceFn.apply(X, Y, a, b, U, eps, q, tol, max_iter,
                                        fixed_iter, range)

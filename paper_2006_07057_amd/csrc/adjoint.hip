@@ -279,6 +279,120 @@ weight_grad_final(const float* __restrict__ u1, const float* __restrict__ u2,
   }
 }
 
+// ------------------------------------------------------------ anchors
+// Gradient with respect to the anchors (q fixed).  With
+// d log phi_k(z)/d u_k = (4/eps)(z - u_k) + (2/(eps q)) u_k and Prop. 3.2,
+// one solve contributes
+//   dW/du_k = -4 [ sum_i p_i Phi~_ik g_k z_i + sum_j p'_j Phi~'_jk g'_k z'_j ]
+//             + 4 (2 - 1/q) m_k u_k,         m_k = z~_k w~_k,
+// where each sum runs over one side (scaling p, the other side's r-vector
+// g); p_i Phi~_ik g_k is a share of transported mass, so in the extended
+// range it is formed as M_p M_g 2^(E_p + L_ik + E_g) within float32 range.
+// The partial kernel walks the rows of one feature matrix with its three
+// weightings (coefficients c_t) and accumulates, for coordinate chunk
+// [dim0, dim0 + dch), A_k = sum_i (sum_t c_t p^t_i Phi~_ik g^t_k) z_i into
+// per-workgroup partials; the final kernel sums them in float64 in a fixed
+// order over both matrices and adds the u_k term.
+constexpr int kAnchorBlocks = 32;
+constexpr int kAnchorCols = 16;   // columns per thread (r <= 4096)
+constexpr int kAnchorDch = 4;     // coordinates per pass
+
+struct AnchorSide {
+  const float* P;        // n x r features (log2 or linear)
+  const float* Z;        // n x d points
+  const float* p[3];     // scalings of the three weightings
+  const float* g[3];     // the matching r-vectors
+  float c[3];
+  int64_t n;
+};
+
+__global__ void __launch_bounds__(kBlock)
+anchor_grad_partial(AnchorSide S, int r, int d, int dim0, int dch,
+                    const int32_t* __restrict__ xr_flag, float* __restrict__ part) {
+  const bool xr = xr_flag && *xr_flag != 0;
+  const int64_t lo = S.n * blockIdx.x / gridDim.x;
+  const int64_t hi = S.n * (blockIdx.x + 1) / gridDim.x;
+  float acc[kAnchorCols][kAnchorDch];
+#pragma unroll
+  for (int j = 0; j < kAnchorCols; ++j)
+#pragma unroll
+    for (int e = 0; e < kAnchorDch; ++e) acc[j][e] = 0.f;
+  for (int64_t i = lo; i < hi; ++i) {
+    float zi[kAnchorDch];
+#pragma unroll
+    for (int e = 0; e < kAnchorDch; ++e)
+      zi[e] = e < dch ? S.Z[i * d + dim0 + e] : 0.f;
+    float pe[3], pm[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      if (xr) {
+        pe[t] = S.p[t][i];
+        pm[t] = S.p[t][S.n + i];
+      } else {
+        pe[t] = 0.f;
+        pm[t] = S.p[t][i];
+      }
+    }
+    const float* Prow = S.P + i * (int64_t)r;
+#pragma unroll
+    for (int j = 0; j < kAnchorCols; ++j) {
+      const int k = threadIdx.x + kBlock * j;
+      if (k >= r) break;
+      const float L = Prow[k];
+      float w = 0.f;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        if (xr)
+          w = fmaf(S.c[t] * pm[t] * S.g[t][r + k],
+                   __builtin_amdgcn_exp2f(pe[t] + L + S.g[t][k]), w);
+        else
+          w = fmaf(S.c[t] * pm[t] * S.g[t][k], L, w);
+      }
+#pragma unroll
+      for (int e = 0; e < kAnchorDch; ++e) acc[j][e] = fmaf(w, zi[e], acc[j][e]);
+    }
+  }
+  float* out = part + (int64_t)blockIdx.x * r * kAnchorDch;
+#pragma unroll
+  for (int j = 0; j < kAnchorCols; ++j) {
+    const int k = threadIdx.x + kBlock * j;
+    if (k >= r) break;
+#pragma unroll
+    for (int e = 0; e < kAnchorDch; ++e) out[(int64_t)k * kAnchorDch + e] = acc[j][e];
+  }
+}
+
+// r-vector entry as a double (pair or linear)
+__device__ __forceinline__ double rvec(const float* g, int r, int k, bool xr) {
+  return xr ? ldexp((double)g[r + k], (int)fmax(fmin((double)g[k], 2000.0), -2000.0))
+            : (double)g[k];
+}
+
+__global__ void __launch_bounds__(kBlock)
+anchor_grad_final(const float* __restrict__ partx, const float* __restrict__ party,
+                  int nblk, int r, int d, int dim0, int dch,
+                  const float* __restrict__ U, double ucoef,
+                  const float* zxy, const float* wxy, const float* zxx,
+                  const float* wxx, const float* zyy, const float* wyy,
+                  const int32_t* __restrict__ xr_flag,
+                  const float* __restrict__ grad_out, float* __restrict__ dU) {
+  const bool xr = xr_flag && *xr_flag != 0;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= r * dch) return;
+  const int k = idx / dch, e = idx % dch;
+  double sum = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    sum += (double)partx[((int64_t)b * r + k) * kAnchorDch + e];
+    sum += (double)party[((int64_t)b * r + k) * kAnchorDch + e];
+  }
+  const double m = rvec(zxy, r, k, xr) * rvec(wxy, r, k, xr) -
+                   0.5 * (rvec(zxx, r, k, xr) * rvec(wxx, r, k, xr) +
+                          rvec(zyy, r, k, xr) * rvec(wyy, r, k, xr));
+  sum += ucoef * m * (double)U[(int64_t)k * d + dim0 + e];
+  const double go = grad_out ? (double)*grad_out : 1.0;
+  dU[(int64_t)k * d + dim0 + e] = (float)(go * sum);
+}
+
 }  // namespace
 
 hipError_t launch_features_backward(const float* X, int64_t n, int d,
@@ -325,6 +439,42 @@ hipError_t launch_weight_grad(const float* u1, const float* u2,
                      s, u1, u2, u3, n, eps, xr_flag, scratch, (int)blocks,
                      grad_out, da);
   return hipGetLastError();
+}
+
+size_t anchor_grad_scratch_floats(int r) {
+  return (size_t)2 * kAnchorBlocks * (size_t)r * kAnchorDch;
+}
+
+hipError_t launch_anchor_grad(const float* X, int64_t n, const float* Y, int64_t m,
+                              int d, const float* U, int r, double q,
+                              const float* Phix, const float* Phiy,
+                              const float* const* u, const float* const* v,
+                              const float* const* w, const float* const* z,
+                              const float* grad_out, const int32_t* xr_flag,
+                              float* scratch, float* dU, hipStream_t s) {
+  if (r > kBlock * kAnchorCols) return hipErrorInvalidValue;
+  float* px = scratch;
+  float* py = scratch + (size_t)kAnchorBlocks * r * kAnchorDch;
+  // solves: 0 = (x, y), 1 = (x, x), 2 = (y, y); coefficients -4 c_s with
+  // c = (1, -1/2, -1/2)
+  AnchorSide SX{Phix, X, {u[0], u[1], v[1]}, {w[0], w[1], z[1]}, {-4.f, 2.f, 2.f}, n};
+  AnchorSide SY{Phiy, Y, {v[0], u[2], v[2]}, {z[0], w[2], z[2]}, {-4.f, 2.f, 2.f}, m};
+  const double ucoef = 4.0 * (2.0 - 1.0 / q);
+  void* tok = prof_begin(kProfAdjoint, s);
+  for (int dim0 = 0; dim0 < d; dim0 += kAnchorDch) {
+    const int dch = d - dim0 < kAnchorDch ? d - dim0 : kAnchorDch;
+    hipLaunchKernelGGL(anchor_grad_partial, dim3(kAnchorBlocks), dim3(kBlock), 0, s, SX,
+                       r, d, dim0, dch, xr_flag, px);
+    hipLaunchKernelGGL(anchor_grad_partial, dim3(kAnchorBlocks), dim3(kBlock), 0, s, SY,
+                       r, d, dim0, dch, xr_flag, py);
+    const int total = r * dch;
+    hipLaunchKernelGGL(anchor_grad_final, dim3((total + kBlock - 1) / kBlock), dim3(kBlock),
+                       0, s, px, py, kAnchorBlocks, r, d, dim0, dch, U, ucoef, z[0], w[0],
+                       z[1], w[1], z[2], w[2], xr_flag, grad_out, dU);
+  }
+  const hipError_t e = hipGetLastError();
+  prof_end(tok, s);
+  return e;
 }
 
 }  // namespace sk

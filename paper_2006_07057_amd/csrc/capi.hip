@@ -675,4 +675,35 @@ int sinkhorn_divergence_backward(const sk_problem* p, const void* state,
   return SK_OK;
 }
 
+size_t sinkhorn_divergence_backward_anchors_workspace_size(const sk_problem* p) {
+  if (check_problem(p) != SK_OK) return 0;
+  return anchor_grad_scratch_floats((int)p->r) * sizeof(float);
+}
+
+int sinkhorn_divergence_backward_anchors(const sk_problem* p, const void* state,
+                                         const float* grad_out, float* dU, void* ws,
+                                         size_t ws_bytes, sk_stream_t stream) {
+  int rc = check_problem(p);
+  if (rc) return rc;
+  if (!state || !dU || !ws) return SK_EINVAL;
+  if (ws_bytes < anchor_grad_scratch_floats((int)p->r) * sizeof(float)) return SK_ENOMEM;
+  sk_state_layout L;
+  layout_of(p->n, p->m, p->r, &L);
+  const float* u[3];
+  const float* v[3];
+  const float* w[3];
+  const float* z[3];
+  for (int k = 0; k < 3; ++k) {
+    u[k] = at<float>(state, L.u[k]);
+    v[k] = at<float>(state, L.v[k]);
+    w[k] = at<float>(state, L.w[k]);
+    z[k] = at<float>(state, L.z[k]);
+  }
+  SK_HIP(launch_anchor_grad(p->X, p->n, p->Y, p->m, (int)p->d, p->U, (int)p->r, p->q,
+                            at<float>(state, L.phix), at<float>(state, L.phiy), u, v, w,
+                            z, grad_out, at<int32_t>(state, L.meta),
+                            static_cast<float*>(ws), dU, S(stream)));
+  return SK_OK;
+}
+
 }  // extern "C"

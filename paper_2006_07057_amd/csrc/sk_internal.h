@@ -116,6 +116,14 @@ hipError_t launch_features_backward(const float* X, int64_t n, int d,
                                     const float* grad_out, int accumulate,
                                     const int32_t* xr_flag, int xr, float* dX,
                                     hipStream_t s);
+size_t anchor_grad_scratch_floats(int r);
+hipError_t launch_anchor_grad(const float* X, int64_t n, const float* Y, int64_t m,
+                              int d, const float* U, int r, double q,
+                              const float* Phix, const float* Phiy,
+                              const float* const* u, const float* const* v,
+                              const float* const* w, const float* const* z,
+                              const float* grad_out, const int32_t* xr_flag,
+                              float* scratch, float* dU, hipStream_t s);
 hipError_t launch_weight_grad(const float* u1, const float* u2,
                               const float* u3, int64_t n, double eps,
                               const float* grad_out, const int32_t* xr_flag,

@@ -430,6 +430,43 @@ def test_gradients_match_oracle(api, rng_mode):
 
 
 @pytest.mark.parametrize("rng_mode", RANGES)
+@pytest.mark.parametrize("n,m,d,r,eps", [(300, 250, 3, 256, 0.7), (500, 420, 2, 64, 0.5),
+                                         (260, 300, 16, 100, 1.0)])
+def test_anchor_gradients_match_oracle(api, rng_mode, n, m, d, r, eps):
+    """Anchor gradient (q fixed) vs the oracle's closed form at the same
+    fixed iteration count; r = 100 leaves part of a column sweep empty,
+    d = 16 takes several coordinate chunks."""
+    _say("anchor gradients", rng_mode, n, m, d, r)
+    rng = np.random.default_rng(17 + d)
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    Y = (rng.standard_normal((m, d)) + 0.4).astype(np.float32)
+    a = inputs.dirichlet_weights(rng, n)
+    b = inputs.dirichlet_weights(rng, m)
+    q = oracle.lambert_q(inputs.max_norm(X, Y), eps, d)
+    U = inputs.gaussian_anchors(2, r, d, oracle.sigma2_from_q(q, eps))
+    out, st = api.divergence(dev(X), dev(Y), dev(a), dev(b), dev(U), eps, q,
+                             fixed_iter=300, range=rng_mode)
+    dU = host(api.divergence_backward_anchors(st))
+    rU, div = oracle.divergence_grad_anchors(X, Y, a, b, U, eps, q, fixed_iter=300)
+    assert host(out)[0] == pytest.approx(div.value, rel=DIV_RTOL)
+    rel = np.linalg.norm(dU - rU) / np.linalg.norm(rU)
+    assert rel <= GRAD_RTOL, rel
+    assert np.all(np.abs(dU - rU) <= GRAD_RTOL * np.abs(rU).max() * 10)
+
+
+def test_anchor_gradient_autograd(api):
+    _say("anchor autograd")
+    c, U, eps, q = _divergence_inputs("gauss2d", n=300, m=280)
+    Ud = dev(U).requires_grad_(True)
+    W = api.sinkhorn_divergence(dev(c.X), dev(c.Y), dev(c.a), dev(c.b), Ud, eps, q,
+                                fixed_iter=120)
+    (2.0 * W).backward()
+    rU, div = oracle.divergence_grad_anchors(c.X, c.Y, c.a, c.b, U, eps, q, fixed_iter=120)
+    gU = host(Ud.grad)
+    assert np.linalg.norm(gU - 2 * rU) / np.linalg.norm(2 * rU) <= GRAD_RTOL
+
+
+@pytest.mark.parametrize("rng_mode", RANGES)
 def test_autograd_function(api, rng_mode):
     """torch.autograd.Function wrapper: backward through the adjoint kernels,
     scaled by the incoming gradient."""
