@@ -27,6 +27,9 @@ Pins (tests/test_oracle_pins.py, run without a GPU):
                                of the squared-Euclidean Sinkhorn gradient.
   * divergence_grad_anchors  - central finite differences of the divergence
                                with respect to every anchor coordinate.
+  * arccos_kernel            - 2-D numerical integration of the defining
+                               integral; arccos_features - convergence of the
+                               feature products to the kernel as r grows.
 No function here is "parity unpinned".
 """
 from __future__ import annotations
@@ -42,6 +45,7 @@ __all__ = [
     "lambert_q", "sigma2_from_q", "q_from_sigma2", "divergence_grad_anchors",
     "gaussian_log_features", "gaussian_features", "gaussian_features_scaled",
     "gaussian_kernel", "rf_kernel",
+    "arccos_log_features", "arccos_features", "arccos_kernel", "arccos_features_scaled",
     "SinkhornResult", "sinkhorn", "sinkhorn_dense", "sinkhorn_factored",
     "w_hat", "w_hat_scaled", "Divergence", "divergence",
     "divergence_scaled", "divergence_from_kernels",
@@ -113,6 +117,71 @@ def gaussian_features_scaled(X, U, eps: float, q: float):
     E = gaussian_log_features(X, U, eps, q)
     s = E.max(axis=1)
     return np.exp(E - s[:, None]), s
+
+
+# --------------------------------------------------------------------------
+# Perturbed arc-cosine features (Sec. 3.2, "Arc-cosine kernels"; the lemma on
+# the decomposition of the arc-cosine kernel in the appendix)
+# --------------------------------------------------------------------------
+def arccos_log_features(X, U, s: int, sigma: float, kappa: float) -> np.ndarray:
+    """Natural log of the r + 1 features of the perturbed arc-cosine kernel
+    k_{s,kappa} = k_s + kappa, for anchors U (rows u_k, drawn from
+    N(0, sigma^2 I), sigma > 1):
+        phi_k(x) = r^{-1/2} sigma^{d/2} sqrt(2) max(0, u_k^T x)^s
+                   exp(-||u_k||^2 (1 - 1/sigma^2) / 4),   k = 1..r,
+        phi_{r+1}(x) = sqrt(kappa).
+    The factor sqrt(2) belongs to Theta_s(w) = sqrt(2) max(0, w)^s as the
+    kernel is defined in Sec. 3.2 (with it the map reproduces k_s).  A
+    rectified zero has log -inf; max(0, w)^0 is 1 for w > 0 and 0 else."""
+    X = np.asarray(X, F64)
+    U = np.asarray(U, F64)
+    r, d = U.shape
+    proj = X @ U.T
+    with np.errstate(divide="ignore"):
+        if s == 0:
+            lp = np.where(proj > 0, 0.0, -np.inf)
+        else:
+            lp = s * np.log(np.maximum(proj, 0.0))
+    c = (-0.5 * math.log(r) + 0.5 * d * math.log(sigma) + 0.5 * math.log(2.0)
+         - 0.25 * (1.0 - 1.0 / sigma ** 2) * (U * U).sum(1))
+    out = np.empty((X.shape[0], r + 1))
+    out[:, :r] = lp + c[None, :]
+    out[:, r] = 0.5 * math.log(kappa)
+    return out
+
+
+def arccos_features(X, U, s: int, sigma: float, kappa: float) -> np.ndarray:
+    return np.exp(arccos_log_features(X, U, s, sigma, kappa))
+
+
+def arccos_kernel(X, Y, s: int, kappa: float) -> np.ndarray:
+    """Closed form of k_s (Cho & Saul, 2009): (1/pi) ||x||^s ||y||^s J_s(t)
+    with t the angle between x and y and
+        J_0 = pi - t,  J_1 = sin t + (pi - t) cos t,
+        J_2 = 3 sin t cos t + (pi - t)(1 + 2 cos^2 t);  plus kappa."""
+    X = np.asarray(X, F64)
+    Y = np.asarray(Y, F64)
+    nx = np.linalg.norm(X, axis=1)[:, None]
+    ny = np.linalg.norm(Y, axis=1)[None, :]
+    c = np.clip((X @ Y.T) / (nx * ny), -1.0, 1.0)
+    t = np.arccos(c)
+    if s == 0:
+        J = np.pi - t
+    elif s == 1:
+        J = np.sin(t) + (np.pi - t) * c
+    elif s == 2:
+        J = 3.0 * np.sin(t) * c + (np.pi - t) * (1.0 + 2.0 * c * c)
+    else:
+        raise ValueError("closed form only for s in {0, 1, 2}")
+    return (nx ** s) * (ny ** s) * J / np.pi + kappa
+
+
+def arccos_features_scaled(X, U, s: int, sigma: float, kappa: float):
+    """Row-scaled arc-cosine features: (Phi~, s) with phi = e^s Phi~ and the
+    row maximum of Phi~ equal to 1 (the constant feature keeps it > 0)."""
+    L = arccos_log_features(X, U, s, sigma, kappa)
+    m = L.max(1)
+    return np.exp(L - m[:, None]), m
 
 
 def gaussian_kernel(X, Y, eps: float) -> np.ndarray:

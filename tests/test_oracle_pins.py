@@ -395,3 +395,72 @@ def test_point_gradient_large_r_limit():
         errs[r] = float(np.median(e))
     assert errs[10000] < errs[100] / 3.0
     assert errs[10000] < 0.1
+
+
+# --------------------------------------------------------- arc-cosine kernel
+@pytest.mark.parametrize("s", [0, 1, 2])
+def test_arccos_closed_form_matches_defining_integral(s):
+    """k_s(x, y) = E_{u ~ N(0, I)} Theta_s(u.x) Theta_s(u.y) with
+    Theta_s(w) = sqrt(2) max(0, w)^s, integrated numerically in polar
+    coordinates (d = 2), against the closed form in J_s."""
+    from scipy import integrate
+    rng = _rng(40 + s)
+    X = rng.standard_normal((3, 2))
+    Y = rng.standard_normal((2, 2))
+    K = oracle.arccos_kernel(X, Y, s, kappa=0.0)
+    radial, _ = integrate.quad(lambda p: p ** (2 * s + 1) * math.exp(-p * p / 2), 0, np.inf)
+    alpha = np.linspace(0.0, 2 * np.pi, 400001)[:-1]
+    dirs = np.stack([np.cos(alpha), np.sin(alpha)], 1)
+    for i, x in enumerate(X):
+        for j, y in enumerate(Y):
+            px, py = dirs @ x, dirs @ y
+            if s == 0:
+                ang = np.mean((px > 0) & (py > 0))
+            else:
+                ang = np.mean(np.maximum(px, 0) ** s * np.maximum(py, 0) ** s)
+            val = 2.0 * radial * ang          # (1/2pi) d alpha, rho e^{-rho^2/2} d rho
+            assert K[i, j] == pytest.approx(val, rel=1e-5, abs=1e-9)
+
+
+@pytest.mark.parametrize("s", [0, 1, 2])
+def test_arccos_feature_map_integrates_to_kernel_1d(s):
+    """d = 1: integrating phi(x, u) phi(y, u) against rho = N(0, sigma^2)
+    (the importance weights of the lemma) gives k_s + kappa."""
+    from scipy import integrate
+    sigma, kappa = 1.7, 0.3
+    for x, y in [(0.8, 1.3), (-0.5, -2.0), (0.7, -1.1)]:
+        def phi(z, u):
+            w = max(0.0, u * z)
+            base = w ** s if s > 0 else (1.0 if w > 0 else 0.0)
+            return (sigma ** 0.5) * math.sqrt(2.0) * base * math.exp(-u * u * (1 - 1 / sigma ** 2) / 4)
+        dens = lambda u: math.exp(-u * u / (2 * sigma ** 2)) / (sigma * math.sqrt(2 * math.pi))
+        val = sum(integrate.quad(lambda u: phi(x, u) * phi(y, u) * dens(u), lo, hi)[0]
+                  for lo, hi in ((-np.inf, 0.0), (0.0, np.inf))) + kappa
+        ref = oracle.arccos_kernel(np.array([[x]]), np.array([[y]]), s, kappa)[0, 0]
+        assert val == pytest.approx(ref, rel=1e-7, abs=1e-10)
+
+
+def test_arccos_features_converge_to_kernel():
+    """Products of the r + 1 features are unbiased for k_{s,kappa} and their
+    error shrinks like r^{-1/2} (Prop. 3.1 for this map)."""
+    rng = _rng(50)
+    X = rng.standard_normal((5, 3)) * 0.7
+    Y = rng.standard_normal((4, 3)) * 0.7
+    s, sigma, kappa = 1, 1.4, 0.5
+    K = oracle.arccos_kernel(X, Y, s, kappa)
+    errs = {}
+    for r in (256, 16384):
+        e = []
+        for seed in range(8):
+            U = _rng(1000 + seed).standard_normal((r, 3)) * sigma
+            Kr = oracle.arccos_features(X, U, s, sigma, kappa) @ oracle.arccos_features(Y, U, s, sigma, kappa).T
+            e.append(np.abs(Kr / K - 1).mean())
+        errs[r] = np.median(e)
+    assert errs[16384] < errs[256] / 4
+    # unbiased: the mean over many small draws is close to the kernel
+    acc = np.zeros_like(K)
+    T = 400
+    for seed in range(T):
+        U = _rng(5000 + seed).standard_normal((32, 3)) * sigma
+        acc += oracle.arccos_features(X, U, s, sigma, kappa) @ oracle.arccos_features(Y, U, s, sigma, kappa).T
+    assert np.abs(acc / T / K - 1).max() < 0.05
