@@ -139,6 +139,23 @@ int sinkhorn_features(const float* X, int64_t n, int64_t d, const float* U,
                       int64_t r, double eps, double q, int32_t range,
                       float* Phi, float* logscale, sk_stream_t stream);
 
+/* Row-scaled features of the perturbed arc-cosine kernel k_s + kappa
+ * (Sec. 3.2, "Arc-cosine kernels", and the decomposition lemma of the
+ * appendix).  For anchors u_k (rows of U, drawn from N(0, sigma^2 I),
+ * sigma > 1) and Theta_s(w) = sqrt(2) max(0, w)^s:
+ *   phi_k(x) = r^{-1/2} sigma^{d/2} Theta_s(u_k.x) exp(-||u_k||^2 (1 - 1/sigma^2)/4),
+ *   phi_r(x) = sqrt(kappa)            (one constant feature, index r),
+ * so the call writes r + 1 columns: Phi (n x (r+1)) = exp(log phi - s_i) in
+ * [0, 1] (linear domain; rectified features are exact zeros) and
+ * logscale[i] = s_i = max_k log phi_k(x_i).  Use the result with
+ * SK_RANGE_LINEAR solves (the kernel is >= kappa > 0, well conditioned);
+ * the solver needs (r + 1) % 4 == 0.  max(0, w)^0 is 1 for w > 0, else 0.
+ * Errors: SK_EINVAL (sizes, pointers, s outside 0..8, sigma <= 1,
+ * kappa <= 0), SK_ENOTSUP (r + 1 > SK_MAX_R). */
+int sinkhorn_features_arccos(const float* X, int64_t n, int64_t d, const float* U,
+                             int64_t r, int32_t s, double sigma, double kappa,
+                             float* Phi, float* logscale, sk_stream_t stream);
+
 /* ------------------------------------------------------------- (a3)(a4) */
 /* Workspace bytes needed by sinkhorn_solve for these sizes (host). */
 size_t sinkhorn_solve_workspace_size(int64_t n, int64_t m, int64_t r);

@@ -58,6 +58,8 @@ SIGNATURES = {
                                     ctypes.POINTER(ctypes.c_double)]),
     "sinkhorn_features": (c_i32, [c_void, c_i64, c_i64, c_void, c_i64, c_dbl,
                                   c_dbl, c_i32, c_void, c_void, c_void]),
+    "sinkhorn_features_arccos": (c_i32, [c_void, c_i64, c_i64, c_void, c_i64, c_i32,
+                                         c_dbl, c_dbl, c_void, c_void, c_void]),
     "sinkhorn_solve_workspace_size": (c_size, [c_i64, c_i64, c_i64]),
     "sinkhorn_solve": (c_i32, [c_void, c_i64, c_void, c_i64, c_i64, c_void,
                                c_void, ctypes.POINTER(sk_solve_opts), c_void,

@@ -110,6 +110,52 @@ def features(X: torch.Tensor, U: torch.Tensor, eps: float, q: float,
     return Phi, s
 
 
+def features_arccos(X: torch.Tensor, U: torch.Tensor, s: int, sigma: float,
+                    kappa: float):
+    """Row-scaled perturbed arc-cosine features (linear domain): returns
+    (Phi (n, r + 1), logscale (n,)); the last column is the constant
+    feature sqrt(kappa)."""
+    _need(X, "X")
+    _need(U, "U")
+    n, d = X.shape
+    r = U.shape[0]
+    if U.shape[1] != d:
+        raise ValueError("U must be r x d with the same d as X")
+    Phi = torch.empty((n, r + 1), dtype=torch.float32, device=X.device)
+    ls = torch.empty((n,), dtype=torch.float32, device=X.device)
+    check(lib().sinkhorn_features_arccos(_ptr(X), n, d, _ptr(U), r, int(s), float(sigma),
+                                         float(kappa), _ptr(Phi), _ptr(ls),
+                                         _stream(X.device)), "sinkhorn_features_arccos")
+    return Phi, ls
+
+
+def divergence_arccos(X, Y, a, b, U, s: int, sigma: float, kappa: float, eps: float,
+                      tol=1e-6, max_iter=2000, fixed_iter=0):
+    """Debiased divergence for the arc-cosine kernel (cost -eps log k_{s,kappa}):
+    features of both clouds, then the three solves in one packed launch
+    (linear domain).  Returns (W_bar, infos) (synchronises)."""
+    Px, sx = features_arccos(X, U, s, sigma, kappa)
+    Py, sy = features_arccos(Y, U, s, sigma, kappa)
+    n, m, r1 = Px.shape[0], Py.shape[0], Px.shape[1]
+    dev = X.device
+    buf = lambda k: torch.empty(2 * k, dtype=torch.float32, device=dev)
+    infos = torch.zeros(3 * INFO_BYTES, dtype=torch.uint8, device=dev)
+    keep = []
+    specs = []
+    for t, (P, Q, p, g, sp, sq, rows, cols) in enumerate(
+            ((Px, Py, a, b, sx, sy, n, m), (Px, Px, a, a, sx, sx, n, n),
+             (Py, Py, b, b, sy, sy, m, m))):
+        u, v, w, z = buf(rows), buf(cols), buf(r1), buf(r1)
+        keep.append((u, v, w, z))
+        info = infos[t * INFO_BYTES:(t + 1) * INFO_BYTES]
+        specs.append(solve_spec(P, Q, p, g, u, v, w, z, info, eps=eps, srow=sp, scol=sq))
+    solve_batched(specs, tol=tol, max_iter=max_iter, fixed_iter=fixed_iter,
+                  range=LINEAR, device=dev)
+    rec = parse_infos(infos)
+    wh = rec["w_hat"]
+    return float(wh[0] - 0.5 * (wh[1] + wh[2])), rec
+
+
 # -------------------------------------------------------------- (a3)(a4)
 @dataclasses.dataclass
 class SolveResult:

@@ -409,6 +409,20 @@ int sinkhorn_features(const float* X, int64_t n, int64_t d, const float* U,
   return SK_OK;
 }
 
+int sinkhorn_features_arccos(const float* X, int64_t n, int64_t d, const float* U,
+                             int64_t r, int32_t s_exp, double sigma, double kappa,
+                             float* Phi, float* logscale, sk_stream_t stream) {
+  if (!X || !U || !Phi || !logscale || n < 1 || d < 1 || r < 1) return SK_EINVAL;
+  if (s_exp < 0 || s_exp > 8) return SK_EINVAL;
+  if (!(sigma > 1.0) || !(kappa > 0.0) || !isfinite(sigma) || !isfinite(kappa))
+    return SK_EINVAL;
+  if (r + 1 > SK_MAX_R) return SK_ENOTSUP;
+  if (d > (1 << 20) || n > (int64_t)1 << 40) return SK_EINVAL;
+  SK_HIP(launch_features_arccos(X, n, (int)d, U, (int)r, s_exp, sigma, kappa, Phi,
+                                logscale, S(stream)));
+  return SK_OK;
+}
+
 size_t sinkhorn_solve_workspace_size(int64_t n, int64_t m, int64_t r) {
   if (n < 1 || m < 1 || r < 1 || r > SK_MAX_R) return 0;
   std::vector<SolveSpec> specs(1);

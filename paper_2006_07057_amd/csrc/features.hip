@@ -361,6 +361,74 @@ hipError_t launch_mfma(const FeatDesc& D, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------- arc-cosine map
+// Perturbed arc-cosine kernel k_s + kappa (Sec. 3.2 and the decomposition
+// lemma of the appendix): r rectified projections with importance weights
+// for anchors u_k ~ N(0, sigma^2 I), plus one constant feature sqrt(kappa):
+//   log phi_k(x) = c0 + cu ||u_k||^2 + s log max(0, u_k.x)     (k < r),
+//   c0 = -log(r)/2 + (d/2) log sigma + log(2)/2, cu = -(1 - 1/sigma^2)/4,
+//   log phi_r(x) = log(kappa)/2.
+// Rows are scaled by their maximum (the constant feature keeps it finite);
+// rectified zeros stay exact zeros, so the output is the linear domain.
+constexpr int kArcCols = (SK_MAX_R + 1 + kBlock - 1) / kBlock;
+
+__global__ void __launch_bounds__(kBlock)
+arccos_features_kernel(const float* __restrict__ X, int64_t n, int d,
+                       const float* __restrict__ U, int r, int s, float c0,
+                       float cu, float lk, float* __restrict__ Phi,
+                       float* __restrict__ logscale) {
+  __shared__ float red[kWaves];
+  const int tid = threadIdx.x;
+  const int R1 = r + 1;
+  float cterm[kArcCols];
+#pragma unroll
+  for (int j = 0; j < kArcCols; ++j) {
+    const int k = tid + kBlock * j;
+    cterm[j] = 0.f;
+    if (k < r) {
+      double un = 0.0;
+      for (int e = 0; e < d; ++e) {
+        const double v = U[(int64_t)k * d + e];
+        un += v * v;
+      }
+      cterm[j] = (float)((double)c0 + (double)cu * un);
+    }
+  }
+  for (int64_t row = blockIdx.x; row < n; row += gridDim.x) {
+    const float* x = X + row * (int64_t)d;
+    float lv[kArcCols];
+    float mx = lk;
+#pragma unroll
+    for (int j = 0; j < kArcCols; ++j) {
+      const int k = tid + kBlock * j;
+      lv[j] = -INFINITY;
+      if (k < r) {
+        const float* u = U + (int64_t)k * d;
+        float dot = 0.f;
+        for (int e = 0; e < d; ++e) dot = fmaf(x[e], u[e], dot);
+        if (dot > 0.f) lv[j] = s == 0 ? cterm[j] : fmaf((float)s, logf(dot), cterm[j]);
+        mx = fmaxf(mx, lv[j]);
+      }
+    }
+    mx = group_max<64>(mx);
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = mx;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) mx = fmaxf(mx, red[w]);
+    float* orow = Phi + row * (int64_t)R1;
+#pragma unroll
+    for (int j = 0; j < kArcCols; ++j) {
+      const int k = tid + kBlock * j;
+      if (k < r) orow[k] = expf(lv[j] - mx);
+    }
+    if (tid == 0) {
+      orow[r] = expf(lk - mx);
+      logscale[row] = mx;
+    }
+  }
+}
+
 typedef void (*FeatLaunch)(dim3, hipStream_t, const FeatDesc*, int,
                            const FeatDesc&, int64_t);
 
@@ -496,6 +564,22 @@ hipError_t launch_features_batched(const FeatDesc* host, int count,
 int features_class_rmax(int r) {
   const FeatClass* c = feat_class(r);
   return c ? c->rmax : 0;
+}
+
+hipError_t launch_features_arccos(const float* X, int64_t n, int d, const float* U,
+                                  int r, int s_exp, double sigma, double kappa,
+                                  float* Phi, float* logscale, hipStream_t s) {
+  const float c0 = (float)(-0.5 * log((double)r) + 0.5 * d * log(sigma) + 0.5 * log(2.0));
+  const float cu = (float)(-0.25 * (1.0 - 1.0 / (sigma * sigma)));
+  const float lk = (float)(0.5 * log(kappa));
+  int64_t grid = (int64_t)device_cus() * 8;
+  if (grid > n) grid = n;
+  void* tok = prof_begin(kProfFeatures, s);
+  hipLaunchKernelGGL(arccos_features_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, X, n,
+                     d, U, r, s_exp, c0, cu, lk, Phi, logscale);
+  const hipError_t e = hipGetLastError();
+  prof_end(tok, s);
+  return e;
 }
 
 }  // namespace sk

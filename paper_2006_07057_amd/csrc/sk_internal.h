@@ -116,6 +116,9 @@ hipError_t launch_features_backward(const float* X, int64_t n, int d,
                                     const float* grad_out, int accumulate,
                                     const int32_t* xr_flag, int xr, float* dX,
                                     hipStream_t s);
+hipError_t launch_features_arccos(const float* X, int64_t n, int d, const float* U,
+                                  int r, int s_exp, double sigma, double kappa,
+                                  float* Phi, float* logscale, hipStream_t s);
 size_t anchor_grad_scratch_floats(int r);
 hipError_t launch_anchor_grad(const float* X, int64_t n, const float* Y, int64_t m,
                               int d, const float* U, int r, double q,
