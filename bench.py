@@ -137,8 +137,7 @@ def cpu_baseline(c, U, wl, q, iters_total, sample_rows):
     }
 
 
-SOLVER_SOURCES = ("paper_2006_07057_amd/csrc/solve.hip",
-                  "paper_2006_07057_amd/csrc/sk_internal.h")
+SOLVER_SOURCES = ("paper_2006_07057_amd/csrc/solve.hip",)
 
 
 def measured_traffic(workload, iters):
@@ -180,6 +179,36 @@ def copy_calibration(torch, gib):
 
 
 MFMA_FP32_PEAK_TFLOPS = 157.3
+
+
+def _time(torch, fn, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def time_extras(torch, api, X, Y, U, state, wl, q):
+    """Anchor gradient (one read of each feature matrix per 4 coordinates)
+    and arc-cosine features of X (r + 1 = 1024 columns), on this workload."""
+    n, m, d, r = wl["n"], wl["m"], wl["d"], wl["r"]
+    ms_dU = _time(torch, lambda: api.divergence_backward_anchors(state))
+    bytes_dU = 4.0 * r * (n + m) * ((d + 3) // 4)
+    U1 = U[: r - 1].contiguous()
+    ms_arc = _time(torch, lambda: api.features_arccos(X, U1, 1, 1.5, 0.5))
+    bytes_arc = 4.0 * n * r
+    return {
+        "anchor_gradient": {"ms": ms_dU, "feature_bytes_read": bytes_dU,
+                            "GBps": bytes_dU / (ms_dU / 1e3) / 1e9},
+        "arccos_features": {"ms": ms_arc, "bytes_written": bytes_arc,
+                            "GBps": bytes_arc / (ms_arc / 1e3) / 1e9,
+                            "s": 1, "r_plus_1": r},
+    }
 
 
 def run_features_only(args, wl, torch, api, X, Y, U, q):
@@ -311,6 +340,9 @@ def main(argv=None):
     ap.add_argument("--features-only", action="store_true",
                     help="time only the feature map of both clouds (matrix-core "
                          "roofline for large d)")
+    ap.add_argument("--extras", action="store_true",
+                    help="also time the anchor gradient and the arc-cosine "
+                         "feature map on this workload")
     ap.add_argument("--graph", action="store_true",
                     help="replay the step as a captured HIP graph")
     ap.add_argument("--seed", type=int, default=0)
@@ -468,6 +500,8 @@ def main(argv=None):
             "ours_forward_W_bar": float(o2[0].item()),
             "speedup": ours_rate / plain_rate,
         }
+    if args.extras:
+        rec["next_rows"] = time_extras(torch, api, X, Y, Ud, state, wl, q)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on a host sample", file=sys.stderr,
               flush=True)

@@ -293,7 +293,7 @@ weight_grad_final(const float* __restrict__ u1, const float* __restrict__ u2,
 // [dim0, dim0 + dch), A_k = sum_i (sum_t c_t p^t_i Phi~_ik g^t_k) z_i into
 // per-workgroup partials; the final kernel sums them in float64 in a fixed
 // order over both matrices and adds the u_k term.
-constexpr int kAnchorBlocks = 32;
+constexpr int kAnchorBlocks = 256;
 constexpr int kAnchorCols = 16;   // columns per thread (r <= 4096)
 constexpr int kAnchorDch = 4;     // coordinates per pass
 
