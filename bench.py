@@ -17,6 +17,7 @@ oracle on a bounded sample of the same workload on the host cores.
     python bench.py [--steps K] [--warmup W] [--workload gmm3d_1m]
     python bench.py --workload gauss2d_1k   # + plain dense Sinkhorn comparator
     python bench.py --workload stream       # serving: Poisson request stream
+    python bench.py --workload gauss2d_1m --accelerated   # accelerated solves
 """
 from __future__ import annotations
 
@@ -48,6 +49,11 @@ WORKLOADS = {
     # 200 fixed iterations
     "gauss2d_1k": dict(kind="gauss2d", n=1000, m=1000, d=2, r=128, eps=0.5,
                        sigma2=1.0, tol=1e-6, max_iter=2000, fixed_iter=200),
+    # the same pair of 2-D Gaussians at n = m = 10^6, r = 1024: scalings stay
+    # inside the float32 range, so the linear layout (and the accelerated
+    # solver, which needs it) applies; stop at L1 marginal error < 1e-6
+    "gauss2d_1m": dict(kind="gauss2d", n=1_000_000, m=1_000_000, d=2, r=1024,
+                       eps=0.5, sigma2=1.0, tol=1e-6, max_iter=20000, fixed_iter=0),
 }
 
 
@@ -249,6 +255,96 @@ def run_features_only(args, wl, torch, api, X, Y, U, q):
     return 0
 
 
+def run_accelerated(args, wl, torch, api, X, Y, a, b, U, q):
+    """Accelerated Sinkhorn against Algorithm 1 on the same linear-layout
+    workload and tolerance.  A step is the debiased divergence with its
+    three accelerated solves (features, three persistent launches, fp64
+    reductions) plus the adjoint.  The roofline is the accelerated solver
+    kernel's: two passes over both feature matrices per gradient evaluation
+    and two for the returned scalings, 4 r (rows + cols) bytes each."""
+    kw = dict(tol=wl["tol"], max_iter=wl["max_iter"], fixed_iter=wl["fixed_iter"])
+    state, ws = None, None
+
+    def step():
+        nonlocal state, ws
+        out, state = api.divergence_accelerated(X, Y, a, b, U, wl["eps"], q, L0=1.0,
+                                                state=state, workspace=ws, **kw)
+        ws = state.workspace
+        api.divergence_backward(state)
+        return out
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    api.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out = step()
+        torch.cuda.synchronize()
+        print(f"[bench] step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t0
+    solver_ms, solver_n, _ = api.profile_read(api.PROF_SOLVER)
+    api.profile(False)
+    infos = state.infos()
+    trials = [int(x) for x in state.meta()[1:4]]
+    n, m, r = wl["n"], wl["m"], wl["r"]
+    rows = [(n, m), (n, n), (m, m)]
+    alg_bytes = sum(4.0 * r * (ro + co) * (2 * t + 2) for (ro, co), t in zip(rows, trials))
+    avg_s = solver_ms / max(solver_n, 1) / 1e3
+    achieved = alg_bytes / 3.0 / avg_s / 1e9
+    wbar = float(out[0].item())
+
+    print("[bench] Algorithm 1 (linear layout) at the same tolerance", file=sys.stderr,
+          flush=True)
+    st1, ws1 = None, None
+
+    def step1():
+        nonlocal st1, ws1
+        o, st1 = api.divergence(X, Y, a, b, U, wl["eps"], q, state=st1, workspace=ws1,
+                                range=api.LINEAR, **kw)
+        ws1 = st1.workspace
+        api.divergence_backward(st1)
+        return o
+
+    step1()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        o1 = step1()
+    torch.cuda.synchronize()
+    el1 = time.perf_counter() - t1
+    inf1 = st1.infos()
+    rec = {
+        "metric": "divergences/s with accelerated Sinkhorn solves",
+        "value": args.steps / elapsed, "unit": "divergences/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m, "d": wl["d"], "r": r,
+                   "eps": wl["eps"], "q": q, "tol": wl["tol"],
+                   "max_accepted_steps": wl["max_iter"], "L0": 1.0,
+                   "step": "features + 3 accelerated persistent solves + adjoint"},
+        "roofline": {"bound": "hbm", "kernel": "accel_kernel (accelerated persistent loop)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": alg_bytes / 3.0,
+                     "avg_launch_ms": avg_s * 1e3},
+        "accepted_steps": [int(x) for x in infos["iters"]],
+        "gradient_evaluations": trials,
+        "status": [int(x) for x in infos["status"]],
+        "final_err": [float(x) for x in infos["err"]],
+        "W_bar": wbar,
+        "algorithm1_linear": {"divergences_per_s": args.steps / el1,
+                              "iterations": [int(x) for x in inf1["iters"]],
+                              "status": [int(x) for x in inf1["status"]],
+                              "W_bar": float(o1[0].item())},
+    }
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def run_stream(args, torch, api, inputs):
     """Serving workload: a Poisson stream of uneven divergence requests
     (n, m log-uniform in [2^10, 2^17], d in {2, 3, 16, 64}, r in {64, 256,
@@ -343,6 +439,9 @@ def main(argv=None):
     ap.add_argument("--extras", action="store_true",
                     help="also time the anchor gradient and the arc-cosine "
                          "feature map on this workload")
+    ap.add_argument("--accelerated", action="store_true",
+                    help="accelerated Sinkhorn solves (linear-layout workloads "
+                         "such as gauss2d_1m) against Algorithm 1")
     ap.add_argument("--graph", action="store_true",
                     help="replay the step as a captured HIP graph")
     ap.add_argument("--seed", type=int, default=0)
@@ -376,6 +475,8 @@ def main(argv=None):
     kw = dict(tol=wl["tol"], max_iter=wl["max_iter"], fixed_iter=wl["fixed_iter"])
     if args.features_only:
         return run_features_only(args, wl, torch, api, X, Y, Ud, q)
+    if args.accelerated:
+        return run_accelerated(args, wl, torch, api, X, Y, a, b, Ud, q)
 
     state = None
     ws = None

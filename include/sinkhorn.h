@@ -206,7 +206,9 @@ typedef struct {
                           /* (each sized for the [E | M] pair layout) */
   size_t info;            /* sk_solve_info[3] */
   size_t out;             /* double[4]: W_bar, W_xy, W_xx, W_yy */
-  size_t meta;            /* int32[4]: [0] = numeric domain used */
+  size_t meta;            /* int32[4]: [0] = numeric domain used; [1..3] =
+                             gradient evaluations of the three accelerated
+                             solves (sinkhorn_divergence_accelerated), else 0 */
   size_t total;           /* total bytes */
 } sk_state_layout;
 
@@ -348,6 +350,73 @@ int sinkhorn_divergence_backward_anchors(const sk_problem* p, const void* state,
                                          const float* grad_out, float* dU,
                                          void* ws, size_t ws_bytes,
                                          sk_stream_t stream);
+
+/* ------------------------------------------------- accelerated Sinkhorn */
+/* Workspace bytes for sinkhorn_solve_accelerated on this spec (host); 0 if
+ * the spec is invalid. */
+size_t sinkhorn_solve_accelerated_workspace_size(const sk_solve_spec* spec);
+
+/* Accelerated Sinkhorn (the acceleration remark of Sec. 3.1 and the
+ * accelerated algorithm of the appendix) on the factored kernel
+ * K = Prow Pcol^T: accelerated alternating minimisation of
+ *   phi(eta1, eta2) = log <e^eta1, K e^eta2> - <eta1, a> - <eta2, b>
+ * (minus the dual of Eq. dual-smooth divided by eps).  Every step tries
+ * the Lipschitz estimate L_k / 2 and doubles it until
+ * phi(eta') <= phi(lambda) - ||grad phi(lambda)||^2 / (2L); with
+ * a = 1/(2L) + sqrt(1/(4L^2) + A/L) and tau = a/(A + a), the momentum point
+ * is lambda = tau zeta + (1 - tau) eta, eta' minimises phi exactly over the
+ * block of lambda with the larger gradient norm (a Sinkhorn half-step) and
+ * an accepted step sets zeta -= a grad phi(lambda), eta = eta', A += a.
+ * The iteration runs on the kernel it is given, the row-scaled
+ * Prow Pcol^T, from eta = zeta = 0 (the unscaled kernel from
+ * eta = -(srow, scol)); one gradient evaluation reads each feature matrix
+ * twice.
+ *   spec   one solve, fields as for sinkhorn_solve_batched; the features
+ *          must be in the linear layout (float32 values, not log2), and
+ *          srow / scol (or NULL) are their row log-scales;
+ *   opts   range must be SK_RANGE_LINEAR and warm_start 0.  tol: stop at
+ *          the first momentum point whose gradient L1 norm (the marginal
+ *          error of the normalised plan there) is below tol and return the
+ *          block minimiser from it; max_iter: at most that many accepted
+ *          steps (SK_ENOTCONV after); fixed_iter > 0: exactly that many
+ *          accepted steps, no stopping test;
+ *   L0     starting Lipschitz estimate (> 0, finite; the first step tries
+ *          L0 / 2; the dual's gradient is 2-Lipschitz, so 1 is natural);
+ *   trials device int32 (or NULL): gradient evaluations made (line-search
+ *          trials, each one pass over both matrices for the r-vectors and
+ *          one for the row sums).
+ * Results (device): u (n), v (m) float32 scalings of the returned dual
+ * point, balanced by a common factor; w = Pcol^T v, z = Prow^T u; info:
+ * iters = accepted steps, status, err = L1 error of both marginals of
+ * diag(u) K diag(v), w_hat = eps (a^T log u + b^T log v - log u^T K v) for
+ * the unscaled kernel (the dual F at the returned point).  Per-point state
+ * is float64, features and r-vectors float32.  Runs as one persistent
+ * launch whose workgroups wait on each other (bounded: SK_ETIMEOUT).
+ * ws: device workspace of sinkhorn_solve_accelerated_workspace_size bytes.
+ * Errors: SK_EINVAL (null pointer, n, m, r < 1, eps <= 0, tol < 0, bad
+ * iteration counts, L0 <= 0), SK_ENOTSUP (extended range, warm start,
+ * r % 4 != 0, r > SK_MAX_R), SK_ENOMEM (ws too small), SK_EHIP. */
+int sinkhorn_solve_accelerated(const sk_solve_spec* spec, const sk_solve_opts* opts,
+                               double L0, int32_t* trials, void* ws,
+                               size_t ws_bytes, sk_stream_t stream);
+
+/* Workspace bytes for sinkhorn_divergence_accelerated (host); 0 if the
+ * problem is invalid. */
+size_t sinkhorn_divergence_accelerated_workspace_size(const sk_problem* p);
+
+/* The debiased divergence of sinkhorn_divergence with each of its three
+ * terms solved by accelerated Sinkhorn (sinkhorn_solve_accelerated, one
+ * launch per term, same opts and L0) on linear-layout features: opts->range
+ * must be SK_RANGE_LINEAR.  Each term is the dual F at the returned point,
+ * eps (a^T log u + b^T log v - log u^T K v).  The state is filled as by
+ * sinkhorn_divergence (so sinkhorn_divergence_backward and
+ * sinkhorn_divergence_backward_anchors apply to it), and meta[1..3] hold
+ * the three solves' gradient-evaluation counts.
+ * Errors: as sinkhorn_divergence and sinkhorn_solve_accelerated. */
+int sinkhorn_divergence_accelerated(const sk_problem* p, const sk_solve_opts* opts,
+                                    double L0, double* out, void* state,
+                                    size_t state_bytes, void* ws, size_t ws_bytes,
+                                    sk_stream_t stream);
 
 /* ------------------------------------------------------------ tuning (a6) */
 /* Per-process launch-planning table used by every solve of the feature

@@ -33,7 +33,9 @@ Pins (tests/test_oracle_pins.py, run without a GPU):
                                accelerated gap bound A_k (phi_k - phi*) <=
                                ||eta*||^2/2 at every step; rank-one closed
                                form; first step against finite differences;
-                               line-search doubling.
+                               line-search doubling.  divergence_grad_accelerated
+                               reuses divergence_grad's formulas (pinned there)
+                               on these points.
   * arccos_kernel            - 2-D numerical integration of the defining
                                integral; arccos_features - convergence of the
                                feature products to the kernel as r grows.
@@ -58,6 +60,7 @@ __all__ = [
     "w_hat", "w_hat_scaled", "Divergence", "divergence",
     "divergence_scaled", "divergence_from_kernels",
     "primal_objective", "divergence_grad", "grad_x_exact_kernel",
+    "divergence_grad_accelerated",
 ]
 
 F64 = np.float64
@@ -264,6 +267,8 @@ class AcceleratedResult:
     Ls: list                # accepted Lipschitz estimate of every step
     As: list                # A_k after every accepted step
     phis: list              # phi(eta^k) after every accepted step
+    margins: list           # |G1 - G2| / (G1 + G2) of the block choice, every trial
+    ls_margins: list        # |decrease - required| / required of the test, every trial
 
 
 def accelerated_sinkhorn(apply_K: Callable, apply_Kt: Callable, a, b, tol: float = 1e-6,
@@ -298,7 +303,7 @@ def accelerated_sinkhorn(apply_K: Callable, apply_Kt: Callable, a, b, tol: float
     eta1, eta2 = np.zeros(n), np.zeros(m)
     zeta1, zeta2 = np.zeros(n), np.zeros(m)
     A, L = 0.0, float(L0)
-    trials, blocks, Ls, As, phis = 0, [], [], [], []
+    trials, blocks, Ls, As, phis, margins, ls_margins = 0, [], [], [], [], [], []
     err = math.inf
 
     def phi_at(l1, l2):
@@ -314,7 +319,9 @@ def accelerated_sinkhorn(apply_K: Callable, apply_Kt: Callable, a, b, tol: float
         c = float(e1 @ Ke2)
         g1 = e1 * Ke2 / c - a
         g2 = e2 * Kte1 / c - b
-        if g1 @ g1 >= g2 @ g2:
+        G1, G2 = float(g1 @ g1), float(g2 @ g2)
+        margins.append(abs(G1 - G2) / (G1 + G2) if G1 + G2 > 0 else 0.0)
+        if G1 >= G2:
             block, n1, n2 = 1, np.log(a) - np.log(Ke2) - s2, l2
         else:
             block, n1, n2 = 2, l1, np.log(b) - np.log(Kte1) - s1
@@ -324,10 +331,10 @@ def accelerated_sinkhorn(apply_K: Callable, apply_Kt: Callable, a, b, tol: float
     while True:
         if fixed_iter > 0 and k == fixed_iter:
             return AcceleratedResult(eta1, eta2, k, trials, err, False, zeta1, zeta2,
-                                     blocks, Ls, As, phis)
+                                     blocks, Ls, As, phis, margins, ls_margins)
         if fixed_iter <= 0 and k == max_iter:
             return AcceleratedResult(eta1, eta2, k, trials, err, False, zeta1, zeta2,
-                                     blocks, Ls, As, phis)
+                                     blocks, Ls, As, phis, margins, ls_margins)
         Lt = L / 2.0
         while True:
             ak = 1.0 / (2.0 * Lt) + math.sqrt(1.0 / (4.0 * Lt * Lt) + A / Lt)
@@ -339,11 +346,17 @@ def accelerated_sinkhorn(apply_K: Callable, apply_Kt: Callable, a, b, tol: float
             err = float(np.abs(g1).sum() + np.abs(g2).sum())
             if fixed_iter <= 0 and err < tol:
                 return AcceleratedResult(n1, n2, k, trials, err, True, zeta1, zeta2,
-                                         blocks, Ls, As, phis)
+                                         blocks, Ls, As, phis, margins, ls_margins)
             phi_new = phi_at(n1, n2)
-            if phi_new <= phi_at(l1, l2) - float(g1 @ g1 + g2 @ g2) / (2.0 * Lt):
+            need = float(g1 @ g1 + g2 @ g2) / (2.0 * Lt)
+            drop = phi_at(l1, l2) - phi_new
+            ls_margins.append(abs(drop - need) / need if need > 0 else math.inf)
+            if drop >= need:
                 break
             Lt *= 2.0
+            if not Lt < 1e300:      # the test cannot pass in this precision
+                return AcceleratedResult(eta1, eta2, k, trials, err, False, zeta1, zeta2,
+                                         blocks, Ls, As, phis, margins, ls_margins)
         zeta1 = zeta1 - ak * g1
         zeta2 = zeta2 - ak * g2
         eta1, eta2 = n1, n2
@@ -550,17 +563,55 @@ def divergence_grad(X, Y, a, b, U, eps: float, q: float, tol: float = 1e-13,
     wyy = w_hat(yy.u, yy.v, b, b, eps)
     div = Divergence(wxy - 0.5 * (wxx + wyy), wxy, wxx, wyy, xy, xx, yy)
 
-    dX = (_grad_points_one_side(X, U, eps, Phx, xy.u, Phy.T @ xy.v)
-          - 0.5 * (_grad_points_one_side(X, U, eps, Phx, xx.u, Phx.T @ xx.v)
-                   + _grad_points_one_side(X, U, eps, Phx, xx.v, Phx.T @ xx.u)))
-    dY = (_grad_points_one_side(Y, U, eps, Phy, xy.v, Phx.T @ xy.u)
-          - 0.5 * (_grad_points_one_side(Y, U, eps, Phy, yy.u, Phy.T @ yy.v)
-                   + _grad_points_one_side(Y, U, eps, Phy, yy.v, Phy.T @ yy.u)))
-    da = eps * (np.log(xy.u) - 0.5 * (np.log(xx.u) + np.log(xx.v)))
-    db = eps * (np.log(xy.v) - 0.5 * (np.log(yy.u) + np.log(yy.v)))
-    da = da - da.mean()
-    db = db - db.mean()
+    dX, da, dY, db = _grads_from_scalings(X, Y, U, eps, Phx, Phy, (xy.u, xy.v),
+                                          (xx.u, xx.v), (yy.u, yy.v))
     return dX, da, dY, db, div
+
+
+def _grads_from_scalings(X, Y, U, eps, Phx, Phy, sxy, sxx, syy):
+    """The gradient formulas of divergence_grad applied to the scalings
+    (u, v) of the three terms."""
+    dX = (_grad_points_one_side(X, U, eps, Phx, sxy[0], Phy.T @ sxy[1])
+          - 0.5 * (_grad_points_one_side(X, U, eps, Phx, sxx[0], Phx.T @ sxx[1])
+                   + _grad_points_one_side(X, U, eps, Phx, sxx[1], Phx.T @ sxx[0])))
+    dY = (_grad_points_one_side(Y, U, eps, Phy, sxy[1], Phx.T @ sxy[0])
+          - 0.5 * (_grad_points_one_side(Y, U, eps, Phy, syy[0], Phy.T @ syy[1])
+                   + _grad_points_one_side(Y, U, eps, Phy, syy[1], Phy.T @ syy[0])))
+    da = eps * (np.log(sxy[0]) - 0.5 * (np.log(sxx[0]) + np.log(sxx[1])))
+    db = eps * (np.log(sxy[1]) - 0.5 * (np.log(syy[0]) + np.log(syy[1])))
+    return dX, da - da.mean(), dY, db - db.mean()
+
+
+def divergence_grad_accelerated(X, Y, a, b, U, eps: float, q: float, fixed_iter: int,
+                                L0: float = 1.0):
+    """divergence_grad with each term's dual point taken from
+    accelerated_sinkhorn after `fixed_iter` accepted steps from zero on the
+    row-scaled factored kernel K~ = Phi~_x Phi~_y^T (features divided by
+    their row maxima e^s).  The point eta~ on K~ is the point eta~ - s on
+    the unscaled kernel: u = e^(eta~1 - s_x), v = e^(eta~2 - s_y) enter the
+    same gradient formulas, and each term's value is the dual F of
+    Eq. (dual-smooth) there, F(eta~ - s) = F~(eta~) - eps (<s_x, a> + <s_y, b>).
+    Returns (dX, da, dY, db, (W_bar, W_xy, W_xx, W_yy), (res_xy, res_xx,
+    res_yy))."""
+    a = np.asarray(a, F64)
+    b = np.asarray(b, F64)
+    Phx = gaussian_features(X, U, eps, q)
+    Phy = gaussian_features(Y, U, eps, q)
+    Px, sx = gaussian_features_scaled(X, U, eps, q)
+    Py, sy = gaussian_features_scaled(Y, U, eps, q)
+    runs, vals, sc = [], [], []
+    for P, Q, p, g, sp, sq in ((Px, Py, a, b, sx, sy), (Px, Px, a, a, sx, sx),
+                               (Py, Py, b, b, sy, sy)):
+        res = accelerated_sinkhorn(lambda v, P=P, Q=Q: P @ (Q.T @ v),
+                                   lambda u, P=P, Q=Q: Q @ (P.T @ u), p, g,
+                                   fixed_iter=fixed_iter, L0=L0)
+        runs.append(res)
+        vals.append(dual_value(res.eta1, res.eta2, P @ Q.T, p, g, eps)
+                    - eps * (sp @ p + sq @ g))
+        sc.append((np.exp(res.eta1 - sp), np.exp(res.eta2 - sq)))
+    dX, da, dY, db = _grads_from_scalings(X, Y, U, eps, Phx, Phy, *sc)
+    value = (vals[0] - 0.5 * (vals[1] + vals[2]), vals[0], vals[1], vals[2])
+    return dX, da, dY, db, value, tuple(runs)
 
 
 def _grad_anchors_one_solve(Zr, Zc, U, eps, q, Pr, Pc, p, g):

@@ -82,6 +82,15 @@ SIGNATURES = {
     "sinkhorn_solve_batched": (c_i32, [ctypes.POINTER(sk_solve_spec), c_i32,
                                        ctypes.POINTER(sk_solve_opts), c_void,
                                        c_size, c_void]),
+    "sinkhorn_solve_accelerated_workspace_size": (c_size, [ctypes.POINTER(sk_solve_spec)]),
+    "sinkhorn_solve_accelerated": (c_i32, [ctypes.POINTER(sk_solve_spec),
+                                           ctypes.POINTER(sk_solve_opts), ctypes.c_double,
+                                           c_void, c_void, c_size, c_void]),
+    "sinkhorn_divergence_accelerated_workspace_size": (c_size, [ctypes.POINTER(sk_problem)]),
+    "sinkhorn_divergence_accelerated": (c_i32, [ctypes.POINTER(sk_problem),
+                                                ctypes.POINTER(sk_solve_opts),
+                                                ctypes.c_double, c_void, c_void, c_size,
+                                                c_void, c_size, c_void]),
     "sinkhorn_features_backward": (c_i32, [c_void, c_i64, c_i64, c_void, c_i64,
                                            c_void, c_void, c_void,
                                            ctypes.c_float, c_i32, c_i32, c_void,

@@ -274,6 +274,11 @@ class DivergenceState:
     def out(self):
         return self._view(self.layout.out, 4, torch.float64)
 
+    def meta(self) -> np.ndarray:
+        """int32[4]: numeric domain, then the gradient evaluations of the
+        three accelerated solves (zeros for Algorithm 1)."""
+        return self._view(self.layout.meta, 4, torch.int32).cpu().numpy()
+
 
 def _check_problem_tensors(X, Y, a, b, U):
     _need(X, "X")
@@ -510,6 +515,58 @@ def solve_batched(specs: Sequence[sk_solve_spec], tol=1e-6, max_iter=2000,
                                        _ptr(workspace), workspace.numel(),
                                        _stream(dev)), "sinkhorn_solve_batched")
     return workspace
+
+
+def solve_accelerated_workspace_bytes(spec: sk_solve_spec) -> int:
+    return int(lib().sinkhorn_solve_accelerated_workspace_size(ctypes.byref(spec)))
+
+
+def solve_accelerated(spec: sk_solve_spec, tol=1e-6, max_iter=2000, fixed_iter=0,
+                      L0=1.0, trials: Optional[torch.Tensor] = None,
+                      workspace: Optional[torch.Tensor] = None, device=None):
+    """Accelerated Sinkhorn on one factored kernel whose features are in the
+    linear layout (asynchronous).  trials: optional device int32 tensor of
+    one element receiving the number of gradient evaluations.  Returns the
+    workspace tensor used."""
+    need = solve_accelerated_workspace_bytes(spec)
+    if need == 0:
+        raise ValueError("invalid solve spec")
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    if trials is not None:
+        _need(trials, "trials", dtype=torch.int32, shape=(1,))
+    o = _opts(tol, max_iter, fixed_iter, False, LINEAR)
+    check(lib().sinkhorn_solve_accelerated(ctypes.byref(spec), ctypes.byref(o), float(L0),
+                                           _ptr(trials), _ptr(workspace), workspace.numel(),
+                                           _stream(dev)), "sinkhorn_solve_accelerated")
+    return workspace
+
+
+def divergence_accelerated(X, Y, a, b, U, eps, q, tol=1e-6, max_iter=2000, fixed_iter=0,
+                           L0=1.0, workspace: Optional[torch.Tensor] = None,
+                           state: Optional[DivergenceState] = None):
+    """Debiased divergence with each term solved by accelerated Sinkhorn
+    (linear-layout features).  Returns (out, state) as divergence() does;
+    divergence_backward applies to the state."""
+    _check_problem_tensors(X, Y, a, b, U)
+    if state is None:
+        state = DivergenceState(X, Y, a, b, U, eps, q)
+    state.range = LINEAR
+    need = int(lib().sinkhorn_divergence_accelerated_workspace_size(
+        ctypes.byref(state.problem)))
+    if need == 0:
+        raise ValueError("invalid problem")
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=X.device)
+    out = torch.empty(4, dtype=torch.float64, device=X.device)
+    o = _opts(tol, max_iter, fixed_iter, False, LINEAR)
+    check(lib().sinkhorn_divergence_accelerated(
+        ctypes.byref(state.problem), ctypes.byref(o), float(L0), _ptr(out), _ptr(state.buf),
+        state.buf.numel(), _ptr(workspace), workspace.numel(), _stream(X.device)),
+        "sinkhorn_divergence_accelerated")
+    state.workspace = workspace
+    return out, state
 
 
 def tune_set(r: int, target_bytes: int):

@@ -480,6 +480,83 @@ int sinkhorn_solve_batched(const sk_solve_spec* specs, int32_t count,
   return run_solves(v, opts, ws, ws_bytes, &need, S(stream));
 }
 
+size_t sinkhorn_solve_accelerated_workspace_size(const sk_solve_spec* spec) {
+  std::vector<SolveSpec> sp;
+  if (specs_from(spec, 1, &sp) != SK_OK) return 0;
+  const int g = accel_planned_group(sp[0].n, sp[0].m, sp[0].r);
+  return accel_workspace_bytes(sp[0].n, sp[0].m, sp[0].r, g);
+}
+
+int sinkhorn_solve_accelerated(const sk_solve_spec* spec, const sk_solve_opts* opts,
+                               double L0, int32_t* trials, void* ws, size_t ws_bytes,
+                               sk_stream_t stream) {
+  std::vector<SolveSpec> sp;
+  int rc = specs_from(spec, 1, &sp);
+  if (rc != SK_OK) return rc;
+  if ((rc = check_opts(opts)) != SK_OK) return rc;
+  if (!(L0 > 0.0) || !isfinite(L0)) return SK_EINVAL;
+  if (opts->range != SK_RANGE_LINEAR || opts->warm_start) return SK_ENOTSUP;
+  if (!ws) return SK_EINVAL;
+  const SolveSpec& p = sp[0];
+  const int g = accel_planned_group(p.n, p.m, p.r);
+  if (ws_bytes < accel_workspace_bytes(p.n, p.m, p.r, g)) return SK_ENOMEM;
+  SK_HIP(launch_accelerated(p.Prow, p.Pcol, p.a, p.b, p.srow, p.scol, p.u, p.v, p.w,
+                            p.z, p.info, trials, p.n, p.m, p.r, p.eps, opts->tol,
+                            opts->max_iter, opts->fixed_iter, L0, ws, g, S(stream)));
+  return SK_OK;
+}
+
+size_t sinkhorn_divergence_accelerated_workspace_size(const sk_problem* p) {
+  if (check_problem(p) != SK_OK) return 0;
+  size_t need = 0;
+  const int64_t nr[3] = {p->n, p->n, p->m}, nc[3] = {p->m, p->n, p->m};
+  for (int k = 0; k < 3; ++k) {
+    const int g = accel_planned_group(nr[k], nc[k], (int)p->r);
+    need = std::max(need, accel_workspace_bytes(nr[k], nc[k], (int)p->r, g));
+  }
+  return need;
+}
+
+int sinkhorn_divergence_accelerated(const sk_problem* p, const sk_solve_opts* opts,
+                                    double L0, double* out, void* state,
+                                    size_t state_bytes, void* ws, size_t ws_bytes,
+                                    sk_stream_t stream) {
+  int rc = check_problem(p);
+  if (rc) return rc;
+  rc = check_opts(opts);
+  if (rc) return rc;
+  if (!(L0 > 0.0) || !isfinite(L0)) return SK_EINVAL;
+  if (opts->range != SK_RANGE_LINEAR || opts->warm_start) return SK_ENOTSUP;
+  if (!state || !ws) return SK_EINVAL;
+  sk_state_layout L;
+  layout_of(p->n, p->m, p->r, &L);
+  if (state_bytes < L.total) return SK_ENOMEM;
+  if (ws_bytes < sinkhorn_divergence_accelerated_workspace_size(p)) return SK_ENOMEM;
+  hipStream_t s = S(stream);
+  int32_t* meta = at<int32_t>(state, L.meta);
+  hipLaunchKernelGGL(set_meta_kernel, dim3(1), dim3(64), 0, s, meta, 0);
+  SK_HIP(hipGetLastError());
+  SK_HIP(launch_features(p->X, p->n, (int)p->d, p->U, (int)p->r, p->eps, p->q, 0,
+                         at<float>(state, L.phix), at<float>(state, L.sx), s));
+  SK_HIP(launch_features(p->Y, p->m, (int)p->d, p->U, (int)p->r, p->eps, p->q, 0,
+                         at<float>(state, L.phiy), at<float>(state, L.sy), s));
+  std::vector<SolveSpec> specs;
+  divergence_specs(p, state, &specs);
+  // the three solves run one after the other, reusing the workspace
+  for (int k = 0; k < 3; ++k) {
+    const SolveSpec& q = specs[k];
+    const int g = accel_planned_group(q.n, q.m, q.r);
+    SK_HIP(launch_accelerated(q.Prow, q.Pcol, q.a, q.b, q.srow, q.scol, q.u, q.v, q.w,
+                              q.z, q.info, meta + 1 + k, q.n, q.m, q.r, q.eps, opts->tol,
+                              opts->max_iter, opts->fixed_iter, L0, ws, g, s));
+  }
+  AsmDesc one{at<sk_solve_info>(state, L.info), at<double>(state, L.out), out, nullptr,
+              0, 0};
+  hipLaunchKernelGGL(assemble_kernel, dim3(1), dim3(64), 0, s, nullptr, one, 1);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
 int sinkhorn_tune_set(int64_t r, int64_t target_bytes) {
   if (r < 1 || r > SK_MAX_R || target_bytes < 0) return SK_EINVAL;
   const int cls = class_rmax((int)r);

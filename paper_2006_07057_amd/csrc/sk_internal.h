@@ -133,6 +133,17 @@ hipError_t launch_weight_grad(const float* u1, const float* u2,
                               double* scratch, int scratch_blocks, float* da,
                               hipStream_t s);
 
+// Accelerated Sinkhorn (accel.hip): planned workgroup count, workspace
+// bytes for that count, and the persistent launch (linear domain).
+int accel_planned_group(int64_t n, int64_t m, int r);
+size_t accel_workspace_bytes(int64_t n, int64_t m, int r, int g);
+hipError_t launch_accelerated(const float* Prow, const float* Pcol, const float* a,
+                              const float* b, const float* srow, const float* scol,
+                              float* u, float* v, float* w, float* z, sk_solve_info* info,
+                              int32_t* trials, int64_t n, int64_t m, int r, double eps,
+                              double tol, int max_iter, int fixed_iter, double L0, void* ws,
+                              int g, hipStream_t s);
+
 hipError_t launch_init_ctl(LaunchCtl* ctl, unsigned* bars, int nbars,
                            hipStream_t s);
 
