@@ -166,6 +166,29 @@ def measured_traffic(workload, iters):
     return float(rec["traffic_bytes"])
 
 
+ACCEL_SOURCES = ("paper_2006_07057_amd/csrc/accel.hip",)
+
+
+def measured_accel_traffic(workload, evaluations):
+    """Average HBM bytes per accelerated-solver launch from the committed
+    rocprofv3 counter record, or None when it was taken on other kernel
+    sources or other gradient-evaluation counts."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"accel_kernel_{workload}.traffic.json")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for f in ACCEL_SOURCES:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sources_sha256") != h.hexdigest():
+        return None
+    if list(rec.get("gradient_evaluations", [])) != list(evaluations):
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def copy_calibration(torch, gib):
     """A plain copy of known size: each dispatch reads and writes exactly
     `nbytes`, so hardware byte counters of this dispatch give their scale."""
@@ -324,11 +347,13 @@ def run_accelerated(args, wl, torch, api, X, Y, a, b, U, q):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "d": wl["d"], "r": r,
                    "eps": wl["eps"], "q": q, "tol": wl["tol"],
-                   "max_accepted_steps": wl["max_iter"], "L0": 1.0,
+                   "max_accepted_steps": wl["max_iter"], "fixed_steps": wl["fixed_iter"],
+                   "L0": 1.0,
                    "step": "features + 3 accelerated persistent solves + adjoint"},
         "roofline": {"bound": "hbm", "kernel": "accel_kernel (accelerated persistent loop)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_accel_traffic(args.workload, trials),
                      "algorithmic_bytes_per_launch": alg_bytes / 3.0,
                      "avg_launch_ms": avg_s * 1e3},
         "accepted_steps": [int(x) for x in infos["iters"]],
@@ -444,6 +469,10 @@ def main(argv=None):
                          "such as gauss2d_1m) against Algorithm 1")
     ap.add_argument("--graph", action="store_true",
                     help="replay the step as a captured HIP graph")
+    ap.add_argument("--fixed-iter", type=int, default=None,
+                    help="override the workload's stopping rule with exactly this "
+                         "many iterations (accepted steps for --accelerated), e.g. "
+                         "for short profiled runs")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=100_000)
@@ -465,7 +494,9 @@ def main(argv=None):
     if args.workload == "stream":
         return run_stream(args, torch, api, inputs)
 
-    wl = WORKLOADS[args.workload]
+    wl = dict(WORKLOADS[args.workload])
+    if args.fixed_iter is not None:
+        wl["fixed_iter"] = int(args.fixed_iter)
     print(f"[bench] workload {args.workload}: generating inputs", file=sys.stderr,
           flush=True)
     c, U, q = make_inputs(wl, args.seed, api, inputs)
