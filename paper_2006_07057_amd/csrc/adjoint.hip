@@ -293,8 +293,7 @@ weight_grad_final(const float* __restrict__ u1, const float* __restrict__ u2,
 // [dim0, dim0 + dch), A_k = sum_i (sum_t c_t p^t_i Phi~_ik g^t_k) z_i into
 // per-workgroup partials; the final kernel sums them in float64 in a fixed
 // order over both matrices and adds the u_k term.
-constexpr int kAnchorBlocks = 256;
-constexpr int kAnchorCols = 16;   // columns per thread (r <= 4096)
+constexpr int kAnchorBlocks = 1024;
 constexpr int kAnchorDch = 4;     // coordinates per pass
 
 struct AnchorSide {
@@ -306,60 +305,113 @@ struct AnchorSide {
   int64_t n;
 };
 
+// Thread layout: each thread owns CW float4 column chunks (chunk
+// threadIdx.x + kBlock c), so a row is one coalesced float4 load per chunk;
+// RU rows are loaded before any is used.  The per-column factors c_t g^t_k
+// are loaded once.  The numeric domain is read on the device; the launch
+// runs both domain variants and the one that does not match returns at
+// once.
+template <int CW, int RU, bool XR>
 __global__ void __launch_bounds__(kBlock)
 anchor_grad_partial(AnchorSide S, int r, int d, int dim0, int dch,
                     const int32_t* __restrict__ xr_flag, float* __restrict__ part) {
   const bool xr = xr_flag && *xr_flag != 0;
+  if (xr != XR) return;
+  const int nq = r >> 2;
   const int64_t lo = S.n * blockIdx.x / gridDim.x;
   const int64_t hi = S.n * (blockIdx.x + 1) / gridDim.x;
-  float acc[kAnchorCols][kAnchorDch];
+  // per-column factors: linear cm = c_t g_k; extended range ce = E(g_k),
+  // cm = c_t M(g_k)
+  float ce[3][CW][4], cm[3][CW][4];
 #pragma unroll
-  for (int j = 0; j < kAnchorCols; ++j)
+  for (int t = 0; t < 3; ++t)
 #pragma unroll
-    for (int e = 0; e < kAnchorDch; ++e) acc[j][e] = 0.f;
-  for (int64_t i = lo; i < hi; ++i) {
-    float zi[kAnchorDch];
+    for (int c = 0; c < CW; ++c) {
+      const int q = threadIdx.x + kBlock * c;
 #pragma unroll
-    for (int e = 0; e < kAnchorDch; ++e)
-      zi[e] = e < dch ? S.Z[i * d + dim0 + e] : 0.f;
-    float pe[3], pm[3];
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      if (xr) {
-        pe[t] = S.p[t][i];
-        pm[t] = S.p[t][S.n + i];
-      } else {
-        pe[t] = 0.f;
-        pm[t] = S.p[t][i];
+      for (int e = 0; e < 4; ++e) {
+        const int k = 4 * q + e;
+        const bool ok = q < nq;
+        ce[t][c][e] = XR && ok ? S.g[t][k] : 0.f;
+        cm[t][c][e] = ok ? S.c[t] * (XR ? S.g[t][r + k] : S.g[t][k]) : 0.f;
       }
     }
-    const float* Prow = S.P + i * (int64_t)r;
+  float acc[CW][4][kAnchorDch];
 #pragma unroll
-    for (int j = 0; j < kAnchorCols; ++j) {
-      const int k = threadIdx.x + kBlock * j;
-      if (k >= r) break;
-      const float L = Prow[k];
-      float w = 0.f;
+  for (int c = 0; c < CW; ++c)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int j = 0; j < kAnchorDch; ++j) acc[c][e][j] = 0.f;
+  typedef float nf4 __attribute__((ext_vector_type(4)));
+  for (int64_t i0 = lo; i0 < hi; i0 += RU) {
+    nf4 L[RU][CW];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int64_t i = i0 + u < hi ? i0 + u : hi - 1;
+      const float* row = S.P + i * (int64_t)r;
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        const int q = threadIdx.x + kBlock * c;
+        L[u][c] = q < nq ? __builtin_nontemporal_load((const nf4*)(row + 4 * q))
+                         : nf4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int64_t i = i0 + u;
+      if (i >= hi) break;
+      float zi[kAnchorDch];
+#pragma unroll
+      for (int j = 0; j < kAnchorDch; ++j) zi[j] = j < dch ? S.Z[i * d + dim0 + j] : 0.f;
+      float pe[3], pm[3];
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
-        if (xr)
-          w = fmaf(S.c[t] * pm[t] * S.g[t][r + k],
-                   __builtin_amdgcn_exp2f(pe[t] + L + S.g[t][k]), w);
-        else
-          w = fmaf(S.c[t] * pm[t] * S.g[t][k], L, w);
+        pe[t] = XR ? S.p[t][i] : 0.f;
+        pm[t] = XR ? S.p[t][S.n + i] : S.p[t][i];
       }
 #pragma unroll
-      for (int e = 0; e < kAnchorDch; ++e) acc[j][e] = fmaf(w, zi[e], acc[j][e]);
+      for (int c = 0; c < CW; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float Lv = L[u][c][e];
+          float w;
+          if (XR) {
+            w = 0.f;
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+              w = fmaf(cm[t][c][e] * pm[t],
+                       __builtin_amdgcn_exp2f(pe[t] + Lv + ce[t][c][e]), w);
+          } else {
+            w = Lv * fmaf(cm[0][c][e], pm[0], fmaf(cm[1][c][e], pm[1], cm[2][c][e] * pm[2]));
+          }
+#pragma unroll
+          for (int j = 0; j < kAnchorDch; ++j) acc[c][e][j] = fmaf(w, zi[j], acc[c][e][j]);
+        }
     }
   }
   float* out = part + (int64_t)blockIdx.x * r * kAnchorDch;
 #pragma unroll
-  for (int j = 0; j < kAnchorCols; ++j) {
-    const int k = threadIdx.x + kBlock * j;
-    if (k >= r) break;
+  for (int c = 0; c < CW; ++c) {
+    const int q = threadIdx.x + kBlock * c;
+    if (q >= nq) break;
 #pragma unroll
-    for (int e = 0; e < kAnchorDch; ++e) out[(int64_t)k * kAnchorDch + e] = acc[j][e];
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int j = 0; j < kAnchorDch; ++j)
+        out[(int64_t)(4 * q + e) * kAnchorDch + j] = acc[c][e][j];
   }
+}
+
+typedef void (*AnchorPartialFn)(AnchorSide, int, int, int, int, const int32_t*, float*);
+
+template <int CW, int RU>
+void launch_anchor_partial(hipStream_t s, const AnchorSide& S, int r, int d, int dim0,
+                           int dch, const int32_t* xr_flag, float* part) {
+  hipLaunchKernelGGL((anchor_grad_partial<CW, RU, false>), dim3(kAnchorBlocks), dim3(kBlock),
+                     0, s, S, r, d, dim0, dch, xr_flag, part);
+  hipLaunchKernelGGL((anchor_grad_partial<CW, RU, true>), dim3(kAnchorBlocks), dim3(kBlock),
+                     0, s, S, r, d, dim0, dch, xr_flag, part);
 }
 
 // r-vector entry as a double (pair or linear)
@@ -452,7 +504,11 @@ hipError_t launch_anchor_grad(const float* X, int64_t n, const float* Y, int64_t
                               const float* const* w, const float* const* z,
                               const float* grad_out, const int32_t* xr_flag,
                               float* scratch, float* dU, hipStream_t s) {
-  if (r > kBlock * kAnchorCols) return hipErrorInvalidValue;
+  if (r > 4 * kBlock * 4 || r % 4 != 0) return hipErrorInvalidValue;
+  void (*partial)(hipStream_t, const AnchorSide&, int, int, int, int, const int32_t*,
+                  float*) = r <= 4 * kBlock       ? &launch_anchor_partial<1, 4>
+                            : r <= 8 * kBlock     ? &launch_anchor_partial<2, 4>
+                                                  : &launch_anchor_partial<4, 2>;
   float* px = scratch;
   float* py = scratch + (size_t)kAnchorBlocks * r * kAnchorDch;
   // solves: 0 = (x, y), 1 = (x, x), 2 = (y, y); coefficients -4 c_s with
@@ -463,10 +519,8 @@ hipError_t launch_anchor_grad(const float* X, int64_t n, const float* Y, int64_t
   void* tok = prof_begin(kProfAdjoint, s);
   for (int dim0 = 0; dim0 < d; dim0 += kAnchorDch) {
     const int dch = d - dim0 < kAnchorDch ? d - dim0 : kAnchorDch;
-    hipLaunchKernelGGL(anchor_grad_partial, dim3(kAnchorBlocks), dim3(kBlock), 0, s, SX,
-                       r, d, dim0, dch, xr_flag, px);
-    hipLaunchKernelGGL(anchor_grad_partial, dim3(kAnchorBlocks), dim3(kBlock), 0, s, SY,
-                       r, d, dim0, dch, xr_flag, py);
+    partial(s, SX, r, d, dim0, dch, xr_flag, px);
+    partial(s, SY, r, d, dim0, dch, xr_flag, py);
     const int total = r * dch;
     hipLaunchKernelGGL(anchor_grad_final, dim3((total + kBlock - 1) / kBlock), dim3(kBlock),
                        0, s, px, py, kAnchorBlocks, r, d, dim0, dch, U, ucoef, z[0], w[0],

@@ -370,62 +370,111 @@ hipError_t launch_mfma(const FeatDesc& D, hipStream_t s) {
 //   log phi_r(x) = log(kappa)/2.
 // Rows are scaled by their maximum (the constant feature keeps it finite);
 // rectified zeros stay exact zeros, so the output is the linear domain.
-constexpr int kArcCols = (SK_MAX_R + 1 + kBlock - 1) / kBlock;
-
+// One wave per row: lane l owns the output columns 4l + 256c + v (v < 4,
+// c < C), so the row maximum is a wave butterfly and every store is a
+// contiguous 16-byte chunk; anchors sit transposed in LDS when they fit.
+template <int C, bool V4>
 __global__ void __launch_bounds__(kBlock)
 arccos_features_kernel(const float* __restrict__ X, int64_t n, int d,
                        const float* __restrict__ U, int r, int s, float c0,
                        float cu, float lk, float* __restrict__ Phi,
                        float* __restrict__ logscale) {
-  __shared__ float red[kWaves];
-  const int tid = threadIdx.x;
+  __shared__ __align__(16) float Ut[kFeatLdsFloats];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   const int R1 = r + 1;
-  float cterm[kArcCols];
-#pragma unroll
-  for (int j = 0; j < kArcCols; ++j) {
-    const int k = tid + kBlock * j;
-    cterm[j] = 0.f;
-    if (k < r) {
-      double un = 0.0;
-      for (int e = 0; e < d; ++e) {
-        const double v = U[(int64_t)k * d + e];
-        un += v * v;
-      }
-      cterm[j] = (float)((double)c0 + (double)cu * un);
+  const int rp = (R1 + 3) & ~3;
+  const bool in_lds = (int64_t)d * rp <= kFeatLdsFloats;
+  if (in_lds) {
+    for (int idx = threadIdx.x; idx < d * rp; idx += kBlock) {
+      const int dim = idx / rp, k = idx - dim * rp;
+      Ut[idx] = k < r ? U[(int64_t)k * d + dim] : 0.f;
     }
   }
-  for (int64_t row = blockIdx.x; row < n; row += gridDim.x) {
-    const float* x = X + row * (int64_t)d;
-    float lv[kArcCols];
-    float mx = lk;
+  __syncthreads();
+  float cterm[C][4];
 #pragma unroll
-    for (int j = 0; j < kArcCols; ++j) {
-      const int k = tid + kBlock * j;
-      lv[j] = -INFINITY;
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = 4 * lane + 256 * c + v;
+      cterm[c][v] = 0.f;
       if (k < r) {
-        const float* u = U + (int64_t)k * d;
-        float dot = 0.f;
-        for (int e = 0; e < d; ++e) dot = fmaf(x[e], u[e], dot);
-        if (dot > 0.f) lv[j] = s == 0 ? cterm[j] : fmaf((float)s, logf(dot), cterm[j]);
-        mx = fmaxf(mx, lv[j]);
+        double un = 0.0;
+        for (int e = 0; e < d; ++e) {
+          const double uv = U[(int64_t)k * d + e];
+          un += uv * uv;
+        }
+        cterm[c][v] = (float)((double)c0 + (double)cu * un);
       }
     }
-    mx = group_max<64>(mx);
-    __syncthreads();
-    if ((tid & 63) == 0) red[tid >> 6] = mx;
-    __syncthreads();
+  for (int64_t row = (int64_t)blockIdx.x * kWaves + wave; row < n;
+       row += (int64_t)gridDim.x * kWaves) {
+    const float* x = X + row * (int64_t)d;
+    float dot[C][4];
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) mx = fmaxf(mx, red[w]);
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dot[c][v] = 0.f;
+    for (int e = 0; e < d; ++e) {
+      const float xk = x[e];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int col0 = 4 * lane + 256 * c;
+        if (in_lds) {
+          const int cidx = col0 < rp ? col0 : 0;
+          const float4 u4 = *reinterpret_cast<const float4*>(&Ut[e * rp + cidx]);
+          dot[c][0] = fmaf(xk, u4.x, dot[c][0]);
+          dot[c][1] = fmaf(xk, u4.y, dot[c][1]);
+          dot[c][2] = fmaf(xk, u4.z, dot[c][2]);
+          dot[c][3] = fmaf(xk, u4.w, dot[c][3]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int k = col0 + v < r ? col0 + v : 0;
+            dot[c][v] = fmaf(xk, U[(int64_t)k * d + e], dot[c][v]);
+          }
+        }
+      }
+    }
+    float lv[C][4];
+    float mx = -INFINITY;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = 4 * lane + 256 * c + v;
+        float l = -INFINITY;
+        if (k < r) {
+          if (dot[c][v] > 0.f) l = s == 0 ? cterm[c][v] : fmaf((float)s, logf(dot[c][v]), cterm[c][v]);
+        } else if (k == r) {
+          l = lk;
+        }
+        lv[c][v] = l;
+        mx = fmaxf(mx, l);
+      }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
     float* orow = Phi + row * (int64_t)R1;
 #pragma unroll
-    for (int j = 0; j < kArcCols; ++j) {
-      const int k = tid + kBlock * j;
-      if (k < r) orow[k] = expf(lv[j] - mx);
+    for (int c = 0; c < C; ++c) {
+      const int col0 = 4 * lane + 256 * c;
+      if (V4) {
+        if (col0 < R1) {
+          float4 o;
+          o.x = expf(lv[c][0] - mx);
+          o.y = expf(lv[c][1] - mx);
+          o.z = expf(lv[c][2] - mx);
+          o.w = expf(lv[c][3] - mx);
+          *reinterpret_cast<float4*>(orow + col0) = o;
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (col0 + v < R1) orow[col0 + v] = expf(lv[c][v] - mx);
+      }
     }
-    if (tid == 0) {
-      orow[r] = expf(lk - mx);
-      logscale[row] = mx;
-    }
+    if (lane == 0) logscale[row] = mx;
   }
 }
 
@@ -573,10 +622,23 @@ hipError_t launch_features_arccos(const float* X, int64_t n, int d, const float*
   const float cu = (float)(-0.25 * (1.0 - 1.0 / (sigma * sigma)));
   const float lk = (float)(0.5 * log(kappa));
   int64_t grid = (int64_t)device_cus() * 8;
-  if (grid > n) grid = n;
+  const int64_t need = (n + kWaves - 1) / kWaves;
+  if (grid > need) grid = need;
+  const int R1 = r + 1;
+  const int C = (R1 + 255) / 256;
+  const bool v4 = R1 % 4 == 0;
+  typedef void (*ArcFn)(const float*, int64_t, int, const float*, int, int, float, float,
+                        float, float*, float*);
+  ArcFn fn = nullptr;
+#define SK_ARC(CC)                                                              \
+  if (!fn && C <= CC)                                                           \
+    fn = v4 ? &arccos_features_kernel<CC, true> : &arccos_features_kernel<CC, false>;
+  SK_ARC(1) SK_ARC(2) SK_ARC(4) SK_ARC(8) SK_ARC(16)
+#undef SK_ARC
+  if (!fn) return hipErrorInvalidValue;
   void* tok = prof_begin(kProfFeatures, s);
-  hipLaunchKernelGGL(arccos_features_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, X, n,
-                     d, U, r, s_exp, c0, cu, lk, Phi, logscale);
+  hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kBlock), 0, s, X, n, d, U, r, s_exp, c0,
+                     cu, lk, Phi, logscale);
   const hipError_t e = hipGetLastError();
   prof_end(tok, s);
   return e;
