@@ -24,7 +24,9 @@ Pins (tests/test_oracle_pins.py, run without a GPU):
   * w_hat / divergence       - translation closed form for the exact
                                Gaussian kernel, symmetry, permutation.
   * divergence_grad          - central finite differences; large-r limit
-                               of the squared-Euclidean Sinkhorn gradient.
+                               of the squared-Euclidean Sinkhorn gradient;
+                               divergence_grad_scaled equals it where both
+                               apply.
   * divergence_grad_anchors  - central finite differences of the divergence
                                with respect to every anchor coordinate.
   * accelerated_sinkhorn     - (tests/test_accelerated.py) reaches the
@@ -60,7 +62,7 @@ __all__ = [
     "w_hat", "w_hat_scaled", "Divergence", "divergence",
     "divergence_scaled", "divergence_from_kernels",
     "primal_objective", "divergence_grad", "grad_x_exact_kernel",
-    "divergence_grad_accelerated",
+    "divergence_grad_accelerated", "divergence_grad_scaled", "grads_from_scalings",
 ]
 
 F64 = np.float64
@@ -91,7 +93,7 @@ def q_from_sigma2(sigma2: float, eps: float) -> float:
 # Positive features for the Gaussian kernel k(x,y) = exp(-||x-y||^2/eps)
 # --------------------------------------------------------------------------
 def gaussian_log_features(X, U, eps: float, q: float,
-                          chunk: int = 4096) -> np.ndarray:
+                          chunk: Optional[int] = None) -> np.ndarray:
     """log phi_theta(x_i)_k for the Gaussian feature map.
 
     The per-anchor map (Lemma 1, in the form derived in its proof, App. A):
@@ -107,6 +109,8 @@ def gaussian_log_features(X, U, eps: float, q: float,
     const = -0.5 * math.log(r) + 0.25 * d * math.log(2.0 * q)
     unorm = (U * U).sum(1) / (eps * q)
     out = np.empty((n, r), F64)
+    if chunk is None:                    # rows per block of differences (<= 256 MB)
+        chunk = max(1, min(4096, (1 << 25) // max(1, r * d)))
     for s in range(0, n, chunk):
         diff = X[s:s + chunk, None, :] - U[None, :, :]
         d2 = (diff * diff).sum(-1)
@@ -484,16 +488,21 @@ def w_hat_scaled(ut, vt, a, b, sx, sy, eps: float) -> float:
 
 def divergence_scaled(X, Y, a, b, U, eps: float, q: float, tol: float = 1e-6,
                       max_iter: int = 2000, fixed_iter: int = 0,
-                      dense: Optional[bool] = None) -> Divergence:
+                      dense: Optional[bool] = None, features=None) -> Divergence:
     """Same quantity as ``divergence`` computed on the row-scaled features:
     Algorithm 1 on K~ = Phi~_x Phi~_y^T from u~0 = 1 (the image of
     u0 = exp(-s_x) under the scaling), then ``w_hat_scaled``.  The iterates
     are those of ``divergence`` times exp(s); unlike ``divergence`` it
     never forms exp of a raw log-feature, so it also covers workloads whose
     raw features underflow float64 (small eps, large d).  The returned
-    SinkhornResult scalings are the scaled ones (u~, v~)."""
-    Px, sx = gaussian_features_scaled(X, U, eps, q)
-    Py, sy = gaussian_features_scaled(Y, U, eps, q)
+    SinkhornResult scalings are the scaled ones (u~, v~).  ``features``
+    may hold (Phi~_x, s_x, Phi~_y, s_y) already computed by
+    gaussian_features_scaled for these X, Y."""
+    if features is None:
+        Px, sx = gaussian_features_scaled(X, U, eps, q)
+        Py, sy = gaussian_features_scaled(Y, U, eps, q)
+    else:
+        Px, sx, Py, sy = features
     n, m = Px.shape[0], Py.shape[0]
     if dense is None:
         dense = n * m <= 4e7 and n * n <= 4e7 and m * m <= 4e7
@@ -563,12 +572,29 @@ def divergence_grad(X, Y, a, b, U, eps: float, q: float, tol: float = 1e-13,
     wyy = w_hat(yy.u, yy.v, b, b, eps)
     div = Divergence(wxy - 0.5 * (wxx + wyy), wxy, wxx, wyy, xy, xx, yy)
 
-    dX, da, dY, db = _grads_from_scalings(X, Y, U, eps, Phx, Phy, (xy.u, xy.v),
+    dX, da, dY, db = grads_from_scalings(X, Y, U, eps, Phx, Phy, (xy.u, xy.v),
                                           (xx.u, xx.v), (yy.u, yy.v))
     return dX, da, dY, db, div
 
 
-def _grads_from_scalings(X, Y, U, eps, Phx, Phy, sxy, sxx, syy):
+def divergence_grad_scaled(X, Y, a, b, U, eps: float, q: float, tol: float = 1e-13,
+                           max_iter: int = 100000, fixed_iter: int = 0, dense=None):
+    """divergence_grad computed on the row-scaled features (for inputs whose
+    raw features underflow float64, e.g. large d): the gradient formulas only
+    use products u_i phi_k(x_i) = u~_i Phi~_ik and Phi^T v = Phi~^T v~, and
+    log u_xy - (log u_xx + log v_xx)/2 = log u~_xy - (log u~_xx + log v~_xx)/2
+    (the log-scales cancel), so they apply unchanged to the scaled run of
+    divergence_scaled.  Returns (dX, da, dY, db, Divergence)."""
+    Px, sx = gaussian_features_scaled(X, U, eps, q)
+    Py, sy = gaussian_features_scaled(Y, U, eps, q)
+    div = divergence_scaled(X, Y, a, b, U, eps, q, tol=tol, max_iter=max_iter,
+                            fixed_iter=fixed_iter, dense=dense, features=(Px, sx, Py, sy))
+    dX, da, dY, db = grads_from_scalings(X, Y, U, eps, Px, Py, (div.xy.u, div.xy.v),
+                                          (div.xx.u, div.xx.v), (div.yy.u, div.yy.v))
+    return dX, da, dY, db, div
+
+
+def grads_from_scalings(X, Y, U, eps, Phx, Phy, sxy, sxx, syy):
     """The gradient formulas of divergence_grad applied to the scalings
     (u, v) of the three terms."""
     dX = (_grad_points_one_side(X, U, eps, Phx, sxy[0], Phy.T @ sxy[1])
@@ -609,7 +635,7 @@ def divergence_grad_accelerated(X, Y, a, b, U, eps: float, q: float, fixed_iter:
         vals.append(dual_value(res.eta1, res.eta2, P @ Q.T, p, g, eps)
                     - eps * (sp @ p + sq @ g))
         sc.append((np.exp(res.eta1 - sp), np.exp(res.eta2 - sq)))
-    dX, da, dY, db = _grads_from_scalings(X, Y, U, eps, Phx, Phy, *sc)
+    dX, da, dY, db = grads_from_scalings(X, Y, U, eps, Phx, Phy, *sc)
     value = (vals[0] - 0.5 * (vals[1] + vals[2]), vals[0], vals[1], vals[2])
     return dX, da, dY, db, value, tuple(runs)
 

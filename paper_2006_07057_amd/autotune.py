@@ -41,10 +41,10 @@ def class_of(r: int) -> int:
 
 def _problem(n: int, m: int, r: int, d: int, eps: float, seed: int, rng: int, dev):
     c = inputs.gauss2d(seed, n=n, m=m, d=d)
-    sigma2 = 1.0
-    U = inputs.gaussian_anchors(seed, r, d, sigma2)
+    # Lemma 1's bandwidth for these points (valid for every eps and d)
+    q = api.gaussian_q(inputs.max_norm(c.X, c.Y), eps, d)
+    U = inputs.gaussian_anchors(seed, r, d, q * eps / 4.0)
     t = lambda x: torch.from_numpy(x).to(dev)
-    q = 4.0 * sigma2 / eps
     Px, _ = api.features(t(c.X), t(U), eps, q, range=rng)
     Py, _ = api.features(t(c.Y), t(U), eps, q, range=rng)
     return Px, Py, t(c.a), t(c.b)

@@ -1,0 +1,186 @@
+"""Parity at the shapes of the remaining workloads (GPU): the
+differentiation workload shaped like the OT-GAN experiment of Sec. 5
+(n = m = 8192 unit vectors in R^128, eps = 1, r = 2048) and the mixed batch
+of 256 pixel-like problems (d = 784, eps = 10, r in {512, 4096}) under the
+autotuner, at reduced point counts the float64 oracle can follow."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_07057_amd import inputs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+
+def _say(*a):
+    print("[gpu-test]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2006_07057_amd import api as A
+    A.lib()
+    return A
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _oracle_div(X, Y, a, b, U, eps, q, feats):
+    return oracle.divergence_scaled(X, Y, a, b, U, eps, q, tol=1e-12, max_iter=100000,
+                                    dense=True, features=feats)
+
+
+def _splice(P, s, X, rows, U, eps, q):
+    """Features of X with only `rows` recomputed (the others unchanged)."""
+    Pr, sr = oracle.gaussian_features_scaled(X[rows], U, eps, q)
+    P2, s2 = P.copy(), s.copy()
+    P2[rows], s2[rows] = Pr, sr
+    return P2, s2
+
+
+def test_otgan_shaped_gradients_and_descent(api):
+    """Forward divergence and gradients with respect to x and a at
+    n = m = 8192, d = 128, r = 2048, eps = 1: W_bar against the float64
+    oracle (1e-5), the gradients of a 64-point subsample against the
+    oracle's formula (1e-4) and against float64 central differences of
+    the oracle's divergence along random directions supported on that
+    subsample; then 50 gradient steps on x, each lowering W_bar, with the
+    last W_bar checked against the oracle at the final points."""
+    n = m = 8192
+    d, r, eps = 128, 2048, 1.0
+    c = inputs.sphere(0, n=n, m=m, d=d)
+    q = oracle.lambert_q(inputs.max_norm(c.X, c.Y), eps, d)
+    U = inputs.gaussian_anchors(0, r, d, oracle.sigma2_from_q(q, eps))
+    X, Y, a, b, Ud = _dev(c.X), _dev(c.Y), _dev(c.a), _dev(c.b), _dev(U)
+    _say("otgan-shaped forward/backward")
+    out, st = api.divergence(X, Y, a, b, Ud, eps, q, tol=1e-7, max_iter=2000)
+    g = _host(out)
+    assert list(st.infos()["status"]) == [0, 0, 0]
+    dX, da, dY, db = [_host(t) for t in api.divergence_backward(st)]
+
+    _say("oracle features")
+    Px, sx = oracle.gaussian_features_scaled(c.X, U, eps, q)
+    Py, sy = oracle.gaussian_features_scaled(c.Y, U, eps, q)
+    ref = _oracle_div(c.X, c.Y, c.a, c.b, U, eps, q, (Px, sx, Py, sy))
+    assert g[0] == pytest.approx(ref.value, rel=1e-5, abs=1e-7 * abs(ref.w_xy))
+    rX, ra, rY, rb = oracle.grads_from_scalings(
+        c.X, c.Y, U, eps, Px, Py, (ref.xy.u, ref.xy.v), (ref.xx.u, ref.xx.v),
+        (ref.yy.u, ref.yy.v))
+    rng = np.random.default_rng(4)
+    S = np.sort(rng.choice(n, 64, replace=False))
+    rel = np.linalg.norm(dX[S] - rX[S]) / np.linalg.norm(rX[S])
+    assert rel <= 1e-4, rel
+    for gg, rr in ((da, ra), (dY, rY), (db, rb)):
+        assert np.linalg.norm(gg - rr) <= 1e-4 * np.linalg.norm(rr)
+
+    # float64 central differences along directions supported on S
+    X64 = c.X.astype(np.float64)
+    for trial in range(2):
+        D = np.zeros_like(X64)
+        D[S] = rng.standard_normal((64, d))
+        h = 1e-4
+        vals = []
+        for sgn in (1.0, -1.0):
+            Xp = X64 + sgn * h * D
+            P2, s2 = _splice(Px, sx, Xp, S, U, eps, q)
+            vals.append(_oracle_div(Xp, c.Y, c.a, c.b, U, eps, q, (P2, s2, Py, sy)).value)
+        fd = (vals[0] - vals[1]) / (2 * h)
+        got = float((dX * D).sum())
+        scale = np.linalg.norm(rX[S]) * np.linalg.norm(D[S])
+        _say("fd x", trial, got, fd)
+        assert abs(got - fd) <= 1e-4 * scale
+    Da = np.zeros(n)
+    Da[S] = rng.standard_normal(64)
+    Da[S] -= Da[S].mean()
+    h = 1e-7
+    vals = [_oracle_div(c.X, c.Y, c.a.astype(np.float64) + sgn * h * Da, c.b, U, eps, q,
+                        (Px, sx, Py, sy)).value for sgn in (1.0, -1.0)]
+    fd = (vals[0] - vals[1]) / (2 * h)
+    _say("fd a", float(da @ Da), fd)
+    assert abs(float(da @ Da) - fd) <= 1e-4 * np.linalg.norm(ra[S]) * np.linalg.norm(Da)
+
+    # 50 optimisation steps updating x
+    # the gradient of a point carries its weight 1/n: steps of 0.05 n
+    # move points by 5% of their potential's gradient
+    lr = 0.05 * n
+    Xt = X.clone()
+    ws, state = None, None
+    hist = []
+    for step in range(50):
+        o, state = api.divergence(Xt, Y, a, b, Ud, eps, q, tol=1e-7, max_iter=2000,
+                                  state=None, workspace=ws)
+        ws = state.workspace
+        hist.append(float(o[0].item()))
+        if step == 0:
+            slack = 1e-6 * abs(float(o[1].item()))    # float32 noise of W_bar
+        assert list(state.infos()["status"]) == [0, 0, 0]
+        gX = api.divergence_backward(state, need=(True, False, False, False))[0]
+        Xt = Xt - lr * gX
+    _say("descent", hist[0], hist[-1])
+    assert all(hist[k + 1] <= hist[k] + slack for k in range(49))
+    assert hist[-1] < 0.9 * hist[0]
+    Xf = _host(Xt)
+    o, state = api.divergence(Xt, Y, a, b, Ud, eps, q, tol=1e-7, max_iter=2000)
+    Pf, sf = oracle.gaussian_features_scaled(Xf, U, eps, q)
+    reff = _oracle_div(Xf, c.Y, c.a, c.b, U, eps, q, (Pf, sf, Py, sy))
+    assert float(o[0].item()) == pytest.approx(reff.value, rel=1e-5,
+                                               abs=1e-7 * abs(reff.w_xy))
+
+
+def test_mixed_pixel_batch_under_autotuner(api):
+    """256 pixel-like problems (d = 784, eps = 10, r in {512, 4096}, n and m
+    log-uniform in [2^8, 2^11]) in one batched call after the autotuner has
+    set the launch plan of both feature-count classes: every solve
+    converges, and for a sample of problems W_bar and the gradient with
+    respect to x match the float64 oracle."""
+    import torch
+    from paper_2006_07057_amd import autotune
+    eps, d = 10.0, 784
+    sizes = inputs.pixel_batch_sizes(seed=5, count=256, lo=2 ** 8, hi=2 ** 11)
+    probs, host = [], []
+    for i, (n, m, r) in enumerate(sizes):
+        cl = inputs.pixels(100 + i, n=n, m=m, d=d)
+        q = oracle.lambert_q(inputs.max_norm(cl.X, cl.Y), eps, d)
+        U = inputs.gaussian_anchors(100 + i, r, d, oracle.sigma2_from_q(q, eps))
+        probs.append((_dev(cl.X), _dev(cl.Y), _dev(cl.a), _dev(cl.b), _dev(U), eps, q))
+        host.append((cl, U, q))
+    first = {}
+    for (n, m, r) in sizes:
+        first.setdefault(r, (n, m, r))
+    _say("autotune", list(first.values()))
+    autotune.tune(list(first.values()), d=d, eps=eps, iters=4, reps=1)
+    try:
+        _say("batched launch")
+        out, states = api.divergence_batched(probs, tol=1e-6, max_iter=2000)
+        torch.cuda.synchronize()
+        g = _host(out)
+        for st in states:
+            assert list(st.infos()["status"]) == [0, 0, 0]
+        by_r = {512: [], 4096: []}
+        for i, (n, m, r) in enumerate(sizes):
+            by_r[r].append((n + m, i))
+        sample = [i for _, i in sorted(by_r[512])[:3]] + [sorted(by_r[4096])[0][1]]
+        for i in sample:
+            cl, U, q = host[i]
+            _say("oracle problem", i, sizes[i])
+            rX, ra, rY, rb, div = oracle.divergence_grad_scaled(cl.X, cl.Y, cl.a, cl.b, U,
+                                                                eps, q, tol=1e-12)
+            assert g[i, 0] == pytest.approx(div.value, rel=1e-5, abs=1e-7 * abs(div.w_xy))
+            dX = _host(api.divergence_backward(states[i])[0])
+            rel = np.linalg.norm(dX - rX) / np.linalg.norm(rX)
+            assert rel <= 1e-4, (i, rel)
+    finally:
+        autotune.reset()

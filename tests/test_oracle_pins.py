@@ -352,6 +352,36 @@ def test_gradients_match_finite_differences():
     assert abs(da.sum()) < 1e-12 and abs(db.sum()) < 1e-12
 
 
+def test_scaled_gradient_equals_unscaled_and_fd_at_large_d():
+    """divergence_grad_scaled equals divergence_grad where raw features are
+    representable, and at d = 128 (raw features below float64 range for
+    part of the anchors) it matches a central difference of
+    divergence_scaled along a random direction."""
+    X, Y, a, b, U, eps, q = _small_problem(12, 9, 4, r=16, eps=0.7)
+    kw = dict(tol=1e-14, max_iter=1000000)
+    ref = oracle.divergence_grad(X, Y, a, b, U, eps, q, **kw)
+    got = oracle.divergence_grad_scaled(X, Y, a, b, U, eps, q, **kw)
+    for g, r_ in zip(got[:4], ref[:4]):
+        np.testing.assert_allclose(g, r_, rtol=1e-9, atol=1e-12)
+    rng = np.random.default_rng(8)
+    n, m, d, r = 10, 8, 128, 24
+    X = rng.standard_normal((n, d))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    Y = rng.standard_normal((m, d))
+    Y /= np.linalg.norm(Y, axis=1, keepdims=True)
+    a = rng.dirichlet(np.ones(n))
+    b = rng.dirichlet(np.ones(m))
+    eps = 1.0
+    q = oracle.lambert_q(1.0, eps, d)
+    U = rng.standard_normal((r, d)) * math.sqrt(oracle.sigma2_from_q(q, eps))
+    dX, da, dY, db, _ = oracle.divergence_grad_scaled(X, Y, a, b, U, eps, q, **kw)
+    D = rng.standard_normal(X.shape)
+    h = 1e-5
+    fd = (oracle.divergence_scaled(X + h * D, Y, a, b, U, eps, q, **kw).value
+          - oracle.divergence_scaled(X - h * D, Y, a, b, U, eps, q, **kw).value) / (2 * h)
+    assert float((dX * D).sum()) == pytest.approx(fd, rel=1e-6, abs=1e-10)
+
+
 def test_anchor_gradient_matches_finite_differences():
     """Gradient with respect to the anchors (q fixed): central differences
     of the converged divergence in every anchor coordinate."""
