@@ -420,9 +420,27 @@ __device__ __forceinline__ double rvec(const float* g, int r, int k, bool xr) {
             : (double)g[k];
 }
 
+// First reduction stage: chunk y of the workgroup partials (both sides)
+// summed in float64, in block order, for every (column, coordinate) entry.
+constexpr int kAnchorChunks = 64;
+
 __global__ void __launch_bounds__(kBlock)
-anchor_grad_final(const float* __restrict__ partx, const float* __restrict__ party,
-                  int nblk, int r, int d, int dim0, int dch,
+anchor_grad_chunks(const float* __restrict__ partx, const float* __restrict__ party,
+                   int nblk, int entries, double* __restrict__ chunks) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= entries) return;
+  const int b0 = nblk * blockIdx.y / kAnchorChunks;
+  const int b1 = nblk * (blockIdx.y + 1) / kAnchorChunks;
+  double sum = 0.0;
+  for (int b = b0; b < b1; ++b) {
+    sum += (double)partx[(int64_t)b * entries + idx];
+    sum += (double)party[(int64_t)b * entries + idx];
+  }
+  chunks[(int64_t)blockIdx.y * entries + idx] = sum;
+}
+
+__global__ void __launch_bounds__(kBlock)
+anchor_grad_final(const double* __restrict__ chunks, int r, int d, int dim0, int dch,
                   const float* __restrict__ U, double ucoef,
                   const float* zxy, const float* wxy, const float* zxx,
                   const float* wxx, const float* zyy, const float* wyy,
@@ -432,11 +450,10 @@ anchor_grad_final(const float* __restrict__ partx, const float* __restrict__ par
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= r * dch) return;
   const int k = idx / dch, e = idx % dch;
+  const int entries = r * kAnchorDch;
   double sum = 0.0;
-  for (int b = 0; b < nblk; ++b) {
-    sum += (double)partx[((int64_t)b * r + k) * kAnchorDch + e];
-    sum += (double)party[((int64_t)b * r + k) * kAnchorDch + e];
-  }
+  for (int c = 0; c < kAnchorChunks; ++c)
+    sum += chunks[(int64_t)c * entries + k * kAnchorDch + e];
   const double m = rvec(zxy, r, k, xr) * rvec(wxy, r, k, xr) -
                    0.5 * (rvec(zxx, r, k, xr) * rvec(wxx, r, k, xr) +
                           rvec(zyy, r, k, xr) * rvec(wyy, r, k, xr));
@@ -494,7 +511,9 @@ hipError_t launch_weight_grad(const float* u1, const float* u2,
 }
 
 size_t anchor_grad_scratch_floats(int r) {
-  return (size_t)2 * kAnchorBlocks * (size_t)r * kAnchorDch;
+  // two sides of workgroup partials, then the float64 chunk sums
+  return (size_t)2 * kAnchorBlocks * (size_t)r * kAnchorDch +
+         (size_t)2 * kAnchorChunks * (size_t)r * kAnchorDch;
 }
 
 hipError_t launch_anchor_grad(const float* X, int64_t n, const float* Y, int64_t m,
@@ -511,6 +530,9 @@ hipError_t launch_anchor_grad(const float* X, int64_t n, const float* Y, int64_t
                                                   : &launch_anchor_partial<4, 2>;
   float* px = scratch;
   float* py = scratch + (size_t)kAnchorBlocks * r * kAnchorDch;
+  // float64 chunk sums after both sides' partials (8-byte aligned: the
+  // partial arrays hold an even number of floats)
+  double* chunks = reinterpret_cast<double*>(scratch + (size_t)2 * kAnchorBlocks * r * kAnchorDch);
   // solves: 0 = (x, y), 1 = (x, x), 2 = (y, y); coefficients -4 c_s with
   // c = (1, -1/2, -1/2)
   AnchorSide SX{Phix, X, {u[0], u[1], v[1]}, {w[0], w[1], z[1]}, {-4.f, 2.f, 2.f}, n};
@@ -521,9 +543,13 @@ hipError_t launch_anchor_grad(const float* X, int64_t n, const float* Y, int64_t
     const int dch = d - dim0 < kAnchorDch ? d - dim0 : kAnchorDch;
     partial(s, SX, r, d, dim0, dch, xr_flag, px);
     partial(s, SY, r, d, dim0, dch, xr_flag, py);
+    const int entries = r * kAnchorDch;
+    hipLaunchKernelGGL(anchor_grad_chunks,
+                       dim3((entries + kBlock - 1) / kBlock, kAnchorChunks), dim3(kBlock), 0,
+                       s, px, py, kAnchorBlocks, entries, chunks);
     const int total = r * dch;
     hipLaunchKernelGGL(anchor_grad_final, dim3((total + kBlock - 1) / kBlock), dim3(kBlock),
-                       0, s, px, py, kAnchorBlocks, r, d, dim0, dch, U, ucoef, z[0], w[0],
+                       0, s, chunks, r, d, dim0, dch, U, ucoef, z[0], w[0],
                        z[1], w[1], z[2], w[2], xr_flag, grad_out, dU);
   }
   const hipError_t e = hipGetLastError();
