@@ -187,8 +187,9 @@ features_kernel(const FeatDesc* __restrict__ descs, int count, FeatDesc one,
 // The ||x_i||^2 term is the same for every k of a row, so it cancels in
 // E - s and only enters s; what remains, D_ik = c_k + (4/eps) x_i.u_k, is a
 // plain dot product (no cancellation), computed with fp32 matrix-core
-// instructions (16x16x4).  The norms are summed in float64 from the same
-// operands.
+// instructions (16x16x4).  The anchor terms c_k (||u_k||^2 summed in
+// float64) are formed once per launch by a small kernel into a device
+// table; the row norms are summed in float64 from the staged operands.
 //
 // A workgroup owns 64 rows (16 per wave) across all r columns, in column
 // blocks of 64 (four 16-wide tiles per wave).  Operands move in chunks of 32
@@ -196,24 +197,51 @@ features_kernel(const FeatDesc* __restrict__ descs, int count, FeatDesc one,
 // registers one chunk ahead, then into double-buffered LDS tiles padded to
 // 36 floats per row; each lane then reads 8 consecutive k of its row (lane
 // group q takes k in [8q, 8q + 8) of the chunk, an order the sum does not
-// depend on) as two 16-byte LDS reads.  Each column block writes D and
-// updates the row maxima; a final sweep over the workgroup's rows
-// normalises them in place.
+// depend on) as two 16-byte LDS reads.  Each column block updates the row
+// maxima and writes D through an LDS transpose, so every lane stores
+// 16-byte pieces of 256-byte row segments; a final sweep re-reads exactly
+// the pieces each lane wrote (program order) and normalises them in place.
 typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int kMfmaRows = 64;
 constexpr int kMfmaCols = 64;
 constexpr int kMfmaK = 32;
 constexpr int kMfmaPad = 36;  // floats per LDS row (bank spread)
 
+// c_k of the columns, written by anchor_cval_kernel before each MFMA launch
+// (launches on one device run one after another on their stream).
+__device__ float g_anchor_cval[SK_MAX_R];
+
+// One wave per anchor: lanes take coordinates e = lane, lane + 64, ...
+// (coalesced), then a butterfly in a fixed order.
+__global__ void __launch_bounds__(kBlock)
+anchor_cval_kernel(const float* __restrict__ U, int r, int d, float c0, float cu) {
+  const int k = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (k >= r) return;   // whole waves leave together
+  double un = 0.0;
+  for (int e = lane; e < d; e += 64) {
+    const double v = U[(int64_t)k * d + e];
+    un += v * v;
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) un += __shfl_xor(un, off, 64);
+  if (lane == 0) g_anchor_cval[k] = fmaf(cu, (float)un, c0);
+}
+
+constexpr int kMfmaTilePad = 68;  // floats per row of the LDS transpose tile
+
 template <bool LOG2>
 __global__ void __launch_bounds__(kBlock)
 features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
-                     const float* __restrict__ U, int r, float c0, float cu,
+                     const float* __restrict__ U, int r,
                      float scale, float neg2e, float* __restrict__ Phi,
                      float* __restrict__ logscale) {
-  __shared__ float sA[2][kMfmaRows * kMfmaPad];
-  __shared__ float sB[2][kMfmaCols * kMfmaPad];
+  __shared__ __align__(16) float sA[2][kMfmaRows * kMfmaPad];
+  __shared__ __align__(16) float sB[2][kMfmaCols * kMfmaPad];
   __shared__ float s_xn[kMfmaRows];
+  __shared__ float s_max[kMfmaRows];
+  static_assert(kWaves * 16 * kMfmaTilePad <= 2 * kMfmaRows * kMfmaPad,
+                "transpose tiles fit in the A staging buffers");
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -227,6 +255,11 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
   const int nchunks = (d + kMfmaK - 1) / kMfmaK;
   float mrow[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
   double xn = 0.0;
+  // between column blocks the A staging buffers are free (every wave has
+  // passed the k-loop's last barrier, and the next block's first staging
+  // store comes after a barrier): each wave uses a 16 x 64 slice of them to
+  // transpose its D tile
+  float* tile = &sA[0][0] + wave * 16 * kMfmaTilePad;
 
   auto gload = [&](f4v (&ra)[2], f4v (&rb)[2], int cb, int kc) {
     const int k = kc * kMfmaK + 4 * st_f4;
@@ -248,15 +281,15 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
       *reinterpret_cast<f4v*>(&sB[buf][(st_row + 32 * h) * kMfmaPad + 4 * st_f4]) = rb[h];
     }
   };
+  // lane L owns the 16-byte pieces (row L/16 + 4j, columns 4 (L%16) .. +3)
+  // of the wave's 16 x 64 tile, j = 0..3
+  const int prow = lane >> 4;
+  const int pcol = 4 * (lane & 15);
 
   for (int cb = 0; cb < r; cb += kMfmaCols) {
     f4v acc[4];
-    double un[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
-      un[t] = 0.0;
-    }
+    for (int t = 0; t < 4; ++t) acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
     f4v ra[2], rb[2];
     gload(ra, rb, cb, 0);
     __syncthreads();  // previous block's readers are done with buffer 0
@@ -278,9 +311,6 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
         const float* B = &sB[buf][(16 * t + l16) * kMfmaPad + 8 * q];
         const f4v b0 = *reinterpret_cast<const f4v*>(B);
         const f4v b1 = *reinterpret_cast<const f4v*>(B + 4);
-        un[t] += (double)b0.x * b0.x + (double)b0.y * b0.y + (double)b0.z * b0.z +
-                 (double)b0.w * b0.w + (double)b1.x * b1.x + (double)b1.y * b1.y +
-                 (double)b1.z * b1.z + (double)b1.w * b1.w;
 #pragma unroll
         for (int e = 0; e < 4; ++e)
           acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[e], b0[e], acc[t], 0, 0, 0);
@@ -291,46 +321,59 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
       if (kc + 1 < nchunks) lstore(buf ^ 1, ra, rb);
       __syncthreads();
     }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      un[t] += __shfl_xor(un[t], 16, 64);
-      un[t] += __shfl_xor(un[t], 32, 64);
-    }
-    // lane holds acc[t][v] = x_{row_base + 4q + v} . u_{cb + 16t + l16}
+    // lane holds acc[t][v] = x_{row_base + 4q + v} . u_{cb + 16t + l16};
+    // D goes through the wave's LDS tile (row 4q + v, column 16t + l16)
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int col = cb + 16 * t + l16;
-      if (col >= r) continue;
-      const float cval = fmaf(cu, (float)un[t], c0);
+      const float cval = col < r ? g_anchor_cval[col] : 0.f;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t row = row_base + 4 * q + v;
         const float Dv = fmaf(scale, acc[t][v], cval);
-        mrow[v] = fmaxf(mrow[v], Dv);
-        if (row < n) Phi[row * (int64_t)r + col] = Dv;
+        if (col < r) mrow[v] = fmaxf(mrow[v], Dv);
+        tile[(4 * q + v) * kMfmaTilePad + 16 * t + l16] = Dv;
       }
     }
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the tile is written
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int tr = prow + 4 * j;
+      const int64_t row = row_base + tr;
+      const int col = cb + pcol;
+      const f4v val = *reinterpret_cast<const f4v*>(&tile[tr * kMfmaTilePad + pcol]);
+      if (row < n && col < r) *reinterpret_cast<f4v*>(Phi + row * (int64_t)r + col) = val;
+    }
+    __builtin_amdgcn_wave_barrier();      // the tile is read before it is rewritten
   }
   xn += __shfl_xor(xn, 16, 64);
   xn += __shfl_xor(xn, 32, 64);
   if (q == 0) s_xn[wave * 16 + l16] = (float)xn;
 #pragma unroll
   for (int v = 0; v < 4; ++v) mrow[v] = group_max<16>(mrow[v]);
+  if (l16 == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) s_max[wave * 16 + 4 * q + v] = mrow[v];
+  }
   __syncthreads();
-  // normalise the values this lane wrote (program order: its own stores)
+  // normalise the pieces this lane wrote (program order: its own stores)
+  float pmax[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) pmax[j] = s_max[wave * 16 + prow + 4 * j];
   for (int cb = 0; cb < r; cb += kMfmaCols) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int col = cb + 16 * t + l16;
-      if (col >= r) continue;
+    for (int j = 0; j < 4; ++j) {
+      const int64_t row = row_base + prow + 4 * j;
+      const int col = cb + pcol;
+      if (row >= n || col >= r) continue;
+      f4v* p = reinterpret_cast<f4v*>(Phi + row * (int64_t)r + col);
+      f4v x = *p;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = row_base + 4 * q + v;
-        if (row >= n) continue;
-        float* p = Phi + row * (int64_t)r + col;
-        const float x = *p - mrow[v];
-        *p = LOG2 ? x * kLog2e : expf(x);
+      for (int e = 0; e < 4; ++e) {
+        const float y = x[e] - pmax[j];
+        x[e] = LOG2 ? y * kLog2e : expf(y);
       }
+      *p = x;
     }
   }
   if (l16 == 0) {
@@ -348,16 +391,21 @@ hipError_t launch_mfma(const FeatDesc& D, hipStream_t s) {
   const int64_t blocks = (D.n + kMfmaRows - 1) / kMfmaRows;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   const double eps = D.eps, q = D.q;
+  if (D.r > SK_MAX_R || D.r % 4 != 0) return hipErrorInvalidValue;
   const float c0 = (float)(-0.5 * log((double)D.r) + 0.25 * D.d * log(2.0 * q));
   const float cu = (float)(1.0 / (eps * q) - 2.0 / eps);
   const float scale = (float)(4.0 / eps);
   const float neg2e = (float)(-2.0 / eps);
+  hipLaunchKernelGGL(anchor_cval_kernel, dim3((D.r + kWaves - 1) / kWaves), dim3(kBlock), 0, s,
+                     D.U, D.r, D.d, c0, cu);
+  const hipError_t e0 = hipGetLastError();
+  if (e0 != hipSuccess) return e0;
   if (D.log2_out)
     hipLaunchKernelGGL(features_mfma_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), 0,
-                       s, D.X, D.n, D.d, D.U, D.r, c0, cu, scale, neg2e, D.Phi, D.s);
+                       s, D.X, D.n, D.d, D.U, D.r, scale, neg2e, D.Phi, D.s);
   else
     hipLaunchKernelGGL(features_mfma_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), 0,
-                       s, D.X, D.n, D.d, D.U, D.r, c0, cu, scale, neg2e, D.Phi, D.s);
+                       s, D.X, D.n, D.d, D.U, D.r, scale, neg2e, D.Phi, D.s);
   return hipGetLastError();
 }
 
