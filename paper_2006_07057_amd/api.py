@@ -447,6 +447,87 @@ class DivergenceGraph:
         return self.out, (self.grads if self.backward else None)
 
 
+class BatchedDivergenceGraph:
+    """A batch of divergences of fixed, uneven shapes (the packed persistent
+    launches of sinkhorn_divergence_batched, then optionally the adjoint of
+    every problem) captured once as a HIP graph and replayed.  ``shapes``
+    holds (n, m, d, r, eps, q) per problem.  Inputs are copied into static
+    buffers before each replay; ``out`` (count x 4) and the gradients are
+    static tensors overwritten by the next replay."""
+
+    def __init__(self, shapes: Sequence[tuple], tol=1e-6, max_iter=2000, fixed_iter=0,
+                 range=EXTENDED, backward=True, device="cuda:0"):
+        dev = torch.device(device)
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.inputs, self.states = [], []
+        for (n, m, d, r, eps, q) in shapes:
+            X = torch.zeros((n, d), **f32)
+            Y = torch.zeros((m, d), **f32)
+            a = torch.full((n,), 1.0 / n, **f32)
+            b = torch.full((m,), 1.0 / m, **f32)
+            U = torch.zeros((r, d), **f32)
+            st = DivergenceState(X, Y, a, b, U, eps, q)
+            st.range = int(range)
+            self.inputs.append((X, Y, a, b, U))
+            self.states.append(st)
+        count = len(self.states)
+        self.kw = dict(tol=tol, max_iter=max_iter, fixed_iter=fixed_iter, range=range)
+        self.backward = bool(backward)
+        self._arr = (sk_problem * count)(*[s.problem for s in self.states])
+        self._ptrs = (ctypes.c_void_p * count)(*[s.buf.data_ptr() for s in self.states])
+        need = int(lib().sinkhorn_batched_workspace_size(self._arr, count))
+        if need == 0:
+            raise ValueError("invalid batch")
+        self.workspace = torch.empty(max(need, 32768), dtype=torch.uint8, device=dev)
+        self.out = torch.empty((count, 4), dtype=torch.float64, device=dev)
+        self.grads = [tuple(torch.empty_like(t) for t in (X, a, Y, b))
+                      for (X, Y, a, b, _) in self.inputs]
+        self.graph = None
+
+    def _step(self, stream):
+        o = _opts(self.kw["tol"], self.kw["max_iter"], self.kw["fixed_iter"], False,
+                  self.kw["range"])
+        count = len(self.states)
+        check(lib().sinkhorn_divergence_batched(self._arr, count, ctypes.byref(o),
+                                                _ptr(self.out), self._ptrs,
+                                                _ptr(self.workspace), self.workspace.numel(),
+                                                stream), "sinkhorn_divergence_batched")
+        if self.backward:
+            for st, (dX, da, dY, db) in zip(self.states, self.grads):
+                check(lib().sinkhorn_divergence_backward(
+                    ctypes.byref(st.problem), _ptr(st.buf), _ptr(None), _ptr(dX), _ptr(da),
+                    _ptr(dY), _ptr(db), _ptr(self.workspace), self.workspace.numel(),
+                    stream), "sinkhorn_divergence_backward")
+
+    def capture(self):
+        dev = self.out.device
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):  # one eager run before capture
+            self._step(_stream(dev))
+        torch.cuda.current_stream(dev).wait_stream(side)
+        torch.cuda.synchronize(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._step(_stream(dev))
+        return self
+
+    def __call__(self, problems: Sequence[tuple]):
+        """problems: (X, Y, a, b, U) per problem, shapes as captured.  Copies
+        them in and replays (asynchronous).  Returns (out, grads or None)."""
+        if self.graph is None:
+            self.capture()
+        if len(problems) != len(self.inputs):
+            raise ValueError("batch size differs from the captured one")
+        for src, dst in zip(problems, self.inputs):
+            for s_, d_ in zip(src, dst):
+                if tuple(s_.shape) != tuple(d_.shape):
+                    raise ValueError("shape differs from the captured one")
+                d_.copy_(s_)
+        self.graph.replay()
+        return self.out, (self.grads if self.backward else None)
+
+
 def divergence_batched(problems: Sequence[tuple], tol=1e-6, max_iter=2000,
                        fixed_iter=0, range=EXTENDED,
                        workspace: Optional[torch.Tensor] = None):

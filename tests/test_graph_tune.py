@@ -85,6 +85,40 @@ def test_graph_replays_match_eager():
 
 
 @pytest.mark.gpu
+def test_batched_graph_replays_match_eager():
+    """A packed batch of uneven problems (several feature-count classes)
+    captured once with its adjoint: every replay, with eager work between
+    replays, equals an eager batched call bit for bit."""
+    import torch
+    from paper_2006_07057_amd import api
+    rng = np.random.default_rng(7)
+    shapes = []
+    for i in range(12):
+        n, m = (int(x) for x in rng.integers(500, 5000, size=2))
+        d = int(rng.choice([2, 3]))
+        r = int(rng.choice([64, 256, 1024]))
+        shapes.append((n, m, d, r, 0.5, 8.0))
+    G = api.BatchedDivergenceGraph(shapes, tol=1e-6, max_iter=2000)
+    t = lambda x: torch.from_numpy(x).cuda()
+    noise = torch.randn(512, 512, device="cuda")
+    for rep in range(3):
+        probs = [tuple(t(x) for x in _inputs(100 * rep + i, n, m, d, r))
+                 for i, (n, m, d, r, _, _) in enumerate(shapes)]
+        out_g, grads_g = G(probs)
+        out_g = out_g.cpu().numpy().copy()
+        grads_g = [[g.cpu().numpy().copy() for g in gs] for gs in grads_g]
+        for _ in range(3):
+            noise = torch.tanh(noise @ noise.T)
+        torch.cuda.synchronize()
+        out_e, states = api.divergence_batched(
+            [p + (0.5, 8.0) for p in probs], tol=1e-6, max_iter=2000)
+        np.testing.assert_array_equal(out_g, out_e.cpu().numpy())
+        for gs, st in zip(grads_g, states):
+            for g1, g2 in zip(gs, api.divergence_backward(st)):
+                np.testing.assert_array_equal(g1, g2.cpu().numpy())
+
+
+@pytest.mark.gpu
 def test_graph_matches_oracle():
     import torch
     from paper_2006_07057_amd import api
