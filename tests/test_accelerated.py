@@ -161,6 +161,9 @@ def test_acc_argument_errors():
     assert f(ctypes.byref(spec), ctypes.byref(warm), 1.0, None, ws, 1 << 30, None) == _lib.SK_ENOTSUP
     assert f(ctypes.byref(spec), ctypes.byref(lin), 1.0, None, ws, 16, None) == _lib.SK_ENOMEM
     assert f(ctypes.byref(spec), ctypes.byref(lin), 1.0, None, None, 1 << 30, None) == _lib.SK_EINVAL
+    empty = _lib.sk_solve_spec(P, P, P, P, 0, 0, P, P, P, P, P, 0, 12, 8, 1.0)
+    assert f(ctypes.byref(empty), ctypes.byref(lin), 1.0, None, ws, 1 << 30, None) == _lib.SK_EINVAL
+    assert L.sinkhorn_solve_accelerated_workspace_size(ctypes.byref(empty)) == 0
     bad_r = _lib.sk_solve_spec(P, P, P, P, 0, 0, P, P, P, P, P, 10, 12, 6, 1.0)
     assert f(ctypes.byref(bad_r), ctypes.byref(lin), 1.0, None, ws, 1 << 30, None) == _lib.SK_ENOTSUP
     assert L.sinkhorn_solve_accelerated_workspace_size(ctypes.byref(bad_r)) == 0
@@ -275,6 +278,53 @@ def test_acc_tolerance_mode_reaches_optimum(n, m, r):
     sk = oracle.sinkhorn_dense(K, a, b, tol=1e-10, max_iter=200000)
     W = oracle.w_hat(sk.u, sk.v, a, b, 1.0)
     assert info["w_hat"] == pytest.approx(W, rel=1e-5)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,m,r", [(1, 1, 4), (1, 7, 8), (9, 1, 4), (2, 3, 4096),
+                                   (700, 500, 4096)])
+def test_acc_degenerate_and_largest_shapes(n, m, r):
+    """Single-point clouds (one marginal is exact from the first block
+    step) and the largest feature count (r = 4096): fixed steps against
+    the oracle, and tolerance mode reaching the float64 optimum."""
+    A = _gpu_api()
+    Fx, Fy, a, b = _features(n, m, r, seed=3 * n + m + r)
+    Px, Py = Fx.astype(np.float64), Fy.astype(np.float64)
+    ref = oracle.accelerated_sinkhorn(lambda v: Px @ (Py.T @ v), lambda u: Py @ (Px.T @ u),
+                                      a, b, fixed_iter=6)
+    res, info, trials = _run_solve(A, Fx, Fy, a, b, fixed_iter=6)
+    assert info["status"] == 0 and info["iters"] == 6
+    assert trials == ref.trials
+    gu, gv = _gauge_free(np.log(res["u"]), np.log(res["v"]))
+    ru, rv = _gauge_free(ref.eta1, ref.eta2)
+    np.testing.assert_allclose(gu, ru, rtol=0, atol=5e-4)
+    np.testing.assert_allclose(gv, rv, rtol=0, atol=5e-4)
+    res, info, _ = _run_solve(A, Fx, Fy, a, b, tol=1e-6, max_iter=20000)
+    assert info["status"] == 0, info
+    K = Px @ Py.T
+    sk = oracle.sinkhorn_dense(K, a, b, tol=1e-10, max_iter=200000)
+    assert info["w_hat"] == pytest.approx(oracle.w_hat(sk.u, sk.v, a, b, 1.0), rel=1e-5)
+
+
+@pytest.mark.gpu
+def test_acc_rank_one_kernel():
+    """The rank-one degenerate case (every row of the features equal up to
+    scale, r = 4 identical columns): the optimum is the product coupling, of
+    dual value sum a log(a / x) + sum b log(b / y) for K = x y^T."""
+    A = _gpu_api()
+    rng = np.random.default_rng(17)
+    n, m, r = 300, 200, 4
+    x = rng.uniform(0.2, 1.0, n).astype(np.float32)
+    y = rng.uniform(0.2, 1.0, m).astype(np.float32)
+    Fx = np.repeat(x[:, None], r, axis=1).astype(np.float32)
+    Fy = np.repeat(y[:, None], r, axis=1).astype(np.float32)
+    a = inputs.dirichlet_weights(rng, n)
+    b = inputs.dirichlet_weights(rng, m)
+    res, info, _ = _run_solve(A, Fx, Fy, a, b, tol=1e-6, max_iter=5000)
+    assert info["status"] == 0
+    xs, ys = r * x.astype(np.float64), y.astype(np.float64)     # K = (r x) y^T
+    ref = float(a @ np.log(a / xs) + b @ np.log(b / ys))
+    assert info["w_hat"] == pytest.approx(ref, rel=1e-5)
 
 
 def _div_inputs(seed, n, m, d, r, eps):
