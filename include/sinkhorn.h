@@ -389,9 +389,11 @@ size_t sinkhorn_solve_accelerated_workspace_size(const sk_solve_spec* spec);
  * point, balanced by a common factor; w = Pcol^T v, z = Prow^T u; info:
  * iters = accepted steps, status, err = L1 error of both marginals of
  * diag(u) K diag(v), w_hat = eps (a^T log u + b^T log v - log u^T K v) for
- * the unscaled kernel (the dual F at the returned point).  Per-point state
- * is float64, features and r-vectors float32.  Runs as one persistent
- * launch whose workgroups wait on each other (bounded: SK_ETIMEOUT).
+ * the unscaled kernel (the dual F at the returned point).  Features are
+ * read as float32; per-point state, r-vectors and every sum are float64
+ * (w, z and the scalings are returned rounded to float32).  Runs as one
+ * persistent launch whose workgroups wait on each other (bounded:
+ * SK_ETIMEOUT).
  * ws: device workspace of sinkhorn_solve_accelerated_workspace_size bytes.
  * Errors: SK_EINVAL (null pointer, n, m, r < 1, eps <= 0, tol < 0, bad
  * iteration counts, L0 <= 0), SK_ENOTSUP (extended range, warm start,
