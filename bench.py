@@ -370,6 +370,43 @@ def run_accelerated(args, wl, torch, api, X, Y, a, b, U, q):
     return 0
 
 
+def plain_stream(torch, api, reqs, tol=1e-6, max_iter=2000, check_every=10):
+    """Comparator for the serving path: one problem at a time, textbook
+    Sinkhorn on the factored kernel with torch matrix-vector products
+    (v = b / (Py (Px^T u)), u = a / (Px (Py^T v))), features from the library
+    in the linear layout, the L1 column-marginal stop test every
+    `check_every` iterations (one host synchronisation each), the same
+    tolerance and cap.  Returns (seconds, [W_bar or nan per request])."""
+    import math
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+    out = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in reqs:
+        X, Y, a, b, U = t(q.X), t(q.Y), t(q.a), t(q.b), t(q.U)
+        Px, sx = api.features(X, U, q.eps, q.q, range=api.LINEAR)
+        Py, sy = api.features(Y, U, q.eps, q.q, range=api.LINEAR)
+        ws = []
+        for (P, Q, p, w, sp, sq) in ((Px, Py, a, b, sx, sy), (Px, Px, a, a, sx, sx),
+                                      (Py, Py, b, b, sy, sy)):
+            u = torch.ones_like(p)
+            v = w
+            for it in range(1, max_iter + 1):
+                v = w / (Q @ (P.t() @ u))
+                u = p / (P @ (Q.t() @ v))
+                if it % check_every == 0 or it == max_iter:
+                    err = float((v * (Q @ (P.t() @ u)) - w).abs().sum().item())
+                    if not math.isfinite(err) or err < tol:
+                        break
+            wh = q.eps * (torch.dot(p.double(), torch.log(u.double()) - sp.double()) +
+                          torch.dot(w.double(), torch.log(v.double()) - sq.double()))
+            ws.append(float(wh.item()))
+        out.append(ws[0] - 0.5 * (ws[1] + ws[2]))
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, out
+
+
 def run_stream(args, torch, api, inputs):
     """Serving workload: a Poisson stream of uneven divergence requests
     (n, m log-uniform in [2^10, 2^17], d in {2, 3, 16, 64}, r in {64, 256,
@@ -398,6 +435,9 @@ def run_stream(args, torch, api, inputs):
             print(f"[bench] served {len(server.results)}/{len(reqs)} requests",
                   file=sys.stderr, flush=True)
 
+    if args.stream_target > 0:
+        for cls in (4, 8, 16, 32, 64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096):
+            api.tune_set(cls, args.stream_target)
     api.profile(True)
     res = srv.run(reqs, progress=progress)
     solver_ms, solver_n, _ = api.profile_read(api.PROF_SOLVER)
@@ -429,6 +469,8 @@ def run_stream(args, torch, api, inputs):
                    "rate_per_s": args.stream_rate, "n_m": "log-uniform [2^10, 2^17]",
                    "d": [2, 3, 16, 64], "r": [64, 256, 1024], "eps": [0.05, 0.5, 5.0],
                    "tol": 1e-6, "max_iter": 2000, "epoch_iters": args.epoch_iters,
+                   "target_bytes_per_workgroup": {str(c): api.tune_get(c)
+                                                  for c in (64, 256, 1024)},
                    "hbm_budget_bytes": srv.budget},
         "latency_ms": {"p50": st["p50_ms"], "p99": st["p99_ms"]},
         "completed": st["ok"],
@@ -444,6 +486,33 @@ def run_stream(args, torch, api, inputs):
         },
         "features_ms": feat_ms,
     }
+    if args.plain_subset > 0:
+        import dataclasses
+        k = min(args.plain_subset, len(reqs))
+        idx = np.linspace(0, len(reqs) - 1, k).round().astype(int)
+        sub = [dataclasses.replace(reqs[i], arrival=0.0, rid=-1) for i in idx]
+        print(f"[bench] {k} requests: server, then one problem per launch",
+              file=sys.stderr, flush=True)
+        srv2 = serve.Server(epoch_iters=args.epoch_iters)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res2 = srv2.run(sub)
+        torch.cuda.synchronize()
+        ours_s = time.perf_counter() - t0
+        plain_s, plain_w = plain_stream(torch, api, sub)
+        ours = {r.rid: r for r in res2}
+        both = [(ours[j].w_bar, plain_w[j]) for j in range(k)
+                if j in ours and ours[j].status == 0 and np.isfinite(plain_w[j])]
+        rel = [abs(o - p_) / max(abs(o), 1e-12) for o, p_ in both]
+        rec["plain_one_problem_per_launch"] = {
+            "requests": k, "ours_divergences_per_s": k / ours_s,
+            "plain_divergences_per_s": k / plain_s, "speedup": plain_s / ours_s,
+            "ours_converged": sum(1 for r in res2 if r.status == 0),
+            "plain_finite": int(np.isfinite(plain_w).sum()),
+            "compared": len(both),
+            "median_rel_diff": float(np.median(rel)) if rel else None,
+            "kind": "torch matvecs on the factored kernel from the same "
+                    "linear-layout features, stop test every 10 iterations"}
     print(json.dumps(rec), flush=True)
     return 0
 
@@ -458,6 +527,12 @@ def main(argv=None):
     ap.add_argument("--stream-count", type=int, default=2048)
     ap.add_argument("--stream-rate", type=float, default=500.0)
     ap.add_argument("--epoch-iters", type=int, default=50)
+    ap.add_argument("--plain-subset", type=int, default=128,
+                    help="stream mode: also serve this many of the requests at once and "
+                         "run them one problem per launch with plain Sinkhorn (0: skip)")
+    ap.add_argument("--stream-target", type=int, default=0, metavar="BYTES",
+                    help="feature bytes per workgroup and half-step for every "
+                         "solver class during the stream (0: the library's table)")
     ap.add_argument("--features-only", action="store_true",
                     help="time only the feature map of both clouds (matrix-core "
                          "roofline for large d)")
