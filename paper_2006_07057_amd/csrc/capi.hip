@@ -165,13 +165,17 @@ int run_solves(const std::vector<SolveSpec>& specs, const sk_solve_opts* o,
     // workgroups cannot join another).  A launch packing more solves gives
     // each a share of the grid proportional to its work per iteration, so
     // the gangs run side by side instead of queueing for the full grid.
+    // Shares are rounded up: with T = total work / grid, a gang of
+    // ceil(w / T) workgroups finishes within T, while rounding down could
+    // stretch a large solve to nearly 2T and set the launch's length (the
+    // workgroups of early finishers take the small solves' seats in turn).
     std::vector<int> gshare(specs.size());
     if (order.size() > 3) {
       double total = 0.0;
       for (int i : order) total += (double)(specs[i].n + specs[i].m) * specs[i].r;
       for (int i : order) {
         const double w = (double)(specs[i].n + specs[i].m) * specs[i].r;
-        const int64_t gi = (int64_t)((double)capdev * w / total);
+        const int64_t gi = (int64_t)ceil((double)capdev * w / total);
         gshare[i] = (int)std::max<int64_t>(1, std::min<int64_t>(gi, gplan[i]));
       }
     } else {
