@@ -223,6 +223,261 @@ const AdjClass kAdj[] = {
     SK_ACLASS(64, 12), SK_ACLASS(64, 16),
 };
 
+// ------------------------------------------------- matrix-core variant
+// For wider points the contraction V = H U (n x r by r x d) dominates and
+// runs on the fp32 matrix cores (v_mfma 16x16x4).  A workgroup owns 128
+// rows (32 per wave, two 16-row MFMA tiles) and 16 NT coordinates (NT
+// 16-wide tiles).  Per chunk of 32 features it stages, double-buffered in
+// LDS and loaded one chunk ahead into registers: the raw feature rows
+// (coalesced 16-byte reads), the anchor block U[k0 .. k0+32, tile] and the
+// chunk's r-vector entries.  Each lane forms h_ik for the 8 features of
+// its A fragment (rows l16 and l16 + 16, k = 8q .. 8q+7 within the chunk;
+// every h_ik of the tile is formed exactly once) and adds them to its row
+// sums D_i; the MFMA sum order over k is the same for every row.
+typedef float f4v __attribute__((ext_vector_type(4)));
+constexpr int kMmRows = 128;
+constexpr int kMmK = 32;
+constexpr int kMmPadA = 36;   // floats per LDS row of the feature tile
+
+struct AdjTerms {
+  const float* p[3];   // row scalings (extended range: E at [0, n), M at [n, 2n))
+  const float* g[3];   // r-vectors (extended range: E at [0, r), M at [r, 2r))
+  float c[3];
+};
+
+template <int NT>
+__global__ void __launch_bounds__(kBlock)
+features_backward_mfma(const float* __restrict__ X, int64_t n, int d,
+                       const float* __restrict__ U, int r,
+                       const float* __restrict__ Phi, AdjTerms T,
+                       const float* __restrict__ grad_out, int accumulate,
+                       const int32_t* __restrict__ xr_flag, int xr_host,
+                       int col_blocks, float* __restrict__ dX) {
+  constexpr int BN = 16 * NT;
+  constexpr int PB = BN + 4;                       // floats per LDS row of U
+  constexpr int BF4 = kMmK * BN / 4;               // float4 pieces of a U chunk
+  constexpr int BPER = (BF4 + kBlock - 1) / kBlock;
+  __shared__ __align__(16) float sA[2][kMmRows * kMmPadA];
+  __shared__ __align__(16) float sB[2][kMmK * PB];
+  __shared__ __align__(16) float sG[2][6 * kMmK];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int q = lane >> 4;
+  const int l16 = lane & 15;
+  const bool xr = xr_flag ? (*xr_flag != 0) : (xr_host != 0);
+  // blocks are dispatched to the 8 XCDs round-robin: give each XCD a
+  // contiguous run of tiles, so the column blocks of a row block (which
+  // read the same feature rows) share an L2
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  const int L = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int64_t row0 = (int64_t)(L / col_blocks) * kMmRows;
+  const int col0 = (L % col_blocks) * BN;
+  const int nchunks = (r + kMmK - 1) / kMmK;
+
+  // per-row factors of the lane's two A rows
+  float qa[2][3], pe[2][3];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    const int64_t row = row0 + wave * 32 + 16 * rt + l16;
+    const bool rv = row < n;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const bool on = rv && T.p[t] && T.g[t];
+      if (xr) {
+        pe[rt][t] = on ? T.p[t][row] : -1.0e30f;
+        qa[rt][t] = on ? T.c[t] * T.p[t][n + row] : 0.f;
+      } else {
+        pe[rt][t] = 0.f;
+        qa[rt][t] = on ? T.c[t] * T.p[t][row] : 0.f;
+      }
+    }
+  }
+
+  // staging: feature rows st_row + 32h, float4 st_f4 of the chunk
+  const int st_f4 = tid & 7;
+  const int st_row = tid >> 3;
+  f4v ra[4], rb[BPER];
+  float rg = 0.f;
+  auto gload = [&](int kc) {
+    const int k = kc * kMmK + 4 * st_f4;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int64_t row = row0 + st_row + 32 * h;
+      ra[h] = f4v{0.f, 0.f, 0.f, 0.f};
+      if (k < r && row < n) ra[h] = *reinterpret_cast<const f4v*>(Phi + row * (int64_t)r + k);
+    }
+#pragma unroll
+    for (int j = 0; j < BPER; ++j) {
+      const int i = tid + kBlock * j;
+      const int kr = i / (BN / 4), c4 = i % (BN / 4);
+      const int kk = kc * kMmK + kr, dim = col0 + 4 * c4;
+      rb[j] = f4v{0.f, 0.f, 0.f, 0.f};
+      if (i < BF4 && kk < r && dim < d)
+        rb[j] = *reinterpret_cast<const f4v*>(U + (int64_t)kk * d + dim);
+    }
+    if (tid < 6 * kMmK) {
+      // slot s: linear g_s (s < 3); extended range E(g_t) (s = 2t), M(g_t) (s = 2t + 1)
+      const int s = tid / kMmK, kk = kc * kMmK + tid % kMmK;
+      const int t = xr ? s >> 1 : s;
+      const bool mant = xr && (s & 1);
+      const bool on = t < 3 && T.g[t] && kk < r;
+      rg = xr ? (mant ? 0.f : -1.0e30f) : 0.f;
+      if (on) rg = T.g[t][mant ? r + kk : kk];
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+      *reinterpret_cast<f4v*>(&sA[buf][(st_row + 32 * h) * kMmPadA + 4 * st_f4]) = ra[h];
+#pragma unroll
+    for (int j = 0; j < BPER; ++j) {
+      const int i = tid + kBlock * j;
+      if (i < BF4) {
+        const int kr = i / (BN / 4), c4 = i % (BN / 4);
+        *reinterpret_cast<f4v*>(&sB[buf][kr * PB + 4 * c4]) = rb[j];
+      }
+    }
+    if (tid < 6 * kMmK) sG[buf][tid] = rg;
+  };
+
+  f4v acc[2][NT];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[rt][t] = f4v{0.f, 0.f, 0.f, 0.f};
+  float Dp[2] = {0.f, 0.f};
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kc = 0; kc < nchunks; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nchunks) gload(kc + 1);
+    // h for the lane's A fragment: rows l16, l16 + 16; k = 8q + e
+    float hv[2][8];
+    if (xr) {
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) hv[rt][e] = 0.f;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const f4v e0 = *reinterpret_cast<const f4v*>(&sG[buf][(2 * t) * kMmK + 8 * q]);
+        const f4v e1 = *reinterpret_cast<const f4v*>(&sG[buf][(2 * t) * kMmK + 8 * q + 4]);
+        const f4v m0 = *reinterpret_cast<const f4v*>(&sG[buf][(2 * t + 1) * kMmK + 8 * q]);
+        const f4v m1 = *reinterpret_cast<const f4v*>(&sG[buf][(2 * t + 1) * kMmK + 8 * q + 4]);
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+          const float* A = &sA[buf][(wave * 32 + 16 * rt + l16) * kMmPadA + 8 * q];
+          const f4v L0 = *reinterpret_cast<const f4v*>(A);
+          const f4v L1 = *reinterpret_cast<const f4v*>(A + 4);
+          const float pet = pe[rt][t], pmt = qa[rt][t];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            hv[rt][e] = fmaf(pmt * m0[e], __builtin_amdgcn_exp2f(L0[e] + (pet + e0[e])),
+                             hv[rt][e]);
+            hv[rt][4 + e] = fmaf(pmt * m1[e], __builtin_amdgcn_exp2f(L1[e] + (pet + e1[e])),
+                                 hv[rt][4 + e]);
+          }
+        }
+      }
+    } else {
+      f4v g0[3], g1[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        g0[t] = *reinterpret_cast<const f4v*>(&sG[buf][t * kMmK + 8 * q]);
+        g1[t] = *reinterpret_cast<const f4v*>(&sG[buf][t * kMmK + 8 * q + 4]);
+      }
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        const float* A = &sA[buf][(wave * 32 + 16 * rt + l16) * kMmPadA + 8 * q];
+        const f4v x0 = *reinterpret_cast<const f4v*>(A);
+        const f4v x1 = *reinterpret_cast<const f4v*>(A + 4);
+        const float q1 = qa[rt][0], q2 = qa[rt][1], q3 = qa[rt][2];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          hv[rt][e] = x0[e] * (q1 * g0[0][e] + q2 * g0[1][e] + q3 * g0[2][e]);
+          hv[rt][4 + e] = x1[e] * (q1 * g1[0][e] + q2 * g1[1][e] + q3 * g1[2][e]);
+        }
+      }
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+      Dp[rt] += ((hv[rt][0] + hv[rt][1]) + (hv[rt][2] + hv[rt][3])) +
+                ((hv[rt][4] + hv[rt][5]) + (hv[rt][6] + hv[rt][7]));
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      float bv[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) bv[t] = sB[buf][(8 * q + e) * PB + 16 * t + l16];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          acc[rt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(hv[rt][e], bv[t], acc[rt][t], 0, 0, 0);
+    }
+    if (kc + 1 < nchunks) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // D of row l16 (+16): sum over the four k groups
+  const float go = 4.0f * (grad_out ? *grad_out : 1.0f);
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    float D = Dp[rt];
+    D += __shfl_xor(D, 16, 64);
+    D += __shfl_xor(D, 32, 64);
+    // acc[rt][t][v]: row 16 rt + 4q + v of the wave's 32, coordinate 16 t + l16
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float Dr = __shfl(D, 4 * q + v, 64);
+      const int64_t row = row0 + wave * 32 + 16 * rt + 4 * q + v;
+      if (row >= n) continue;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int dim = col0 + 16 * t + l16;
+        if (dim < d) {
+          const float val = go * (X[row * (int64_t)d + dim] * Dr - acc[rt][t][v]);
+          float* o = dX + row * (int64_t)d + dim;
+          *o = accumulate ? *o + val : val;
+        }
+      }
+    }
+  }
+}
+
+typedef void (*MmLaunch)(dim3, hipStream_t, const float*, int64_t, int, const float*, int,
+                         const float*, const AdjTerms&, const float*, int, const int32_t*,
+                         int, int, float*);
+
+template <int NT>
+void launch_mm(dim3 grid, hipStream_t s, const float* X, int64_t n, int d, const float* U,
+               int r, const float* Phi, const AdjTerms& T, const float* go, int acc,
+               const int32_t* xf, int xh, int cb, float* dX) {
+  hipLaunchKernelGGL((features_backward_mfma<NT>), grid, dim3(kBlock), 0, s, X, n, d, U, r,
+                     Phi, T, go, acc, xf, xh, cb, dX);
+}
+
+const MmLaunch kMm[8] = {&launch_mm<1>, &launch_mm<2>, &launch_mm<3>, &launch_mm<4>,
+                         &launch_mm<5>, &launch_mm<6>, &launch_mm<7>, &launch_mm<8>};
+
+// Tiles per workgroup: all of them when d fits in 8 tiles, else the count
+// in 4..8 that leaves the fewest empty tiles (ties: the larger).
+int mm_tiles(int d) {
+  const int tiles = (d + 15) / 16;
+  if (tiles <= 8) return tiles;
+  int best = 8, waste = 1 << 30;
+  for (int nt = 8; nt >= 4; --nt) {
+    const int w = ((tiles + nt - 1) / nt) * nt - tiles;
+    if (w < waste) { waste = w; best = nt; }
+  }
+  return best;
+}
+
+bool use_mm(int d) { return d >= 8 && d % 4 == 0; }
+
 // ------------------------------------------------------------ weight grad
 __device__ __forceinline__ double log_scaling(const float* s, int64_t i,
                                               int64_t n, bool xr) {
@@ -473,6 +728,19 @@ hipError_t launch_features_backward(const float* X, int64_t n, int d,
                                     const int32_t* xr_flag, int xr, float* dX,
                                     hipStream_t s) {
   if (r % 4 != 0) return hipErrorInvalidValue;
+  if (use_mm(d)) {
+    const int nt = mm_tiles(d);
+    const int64_t cb = (d + 16 * nt - 1) / (16 * nt);
+    const int64_t blocks = ((n + kMmRows - 1) / kMmRows) * cb;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const AdjTerms T{{p1, p2, p3}, {g1, g2, g3}, {c1, c2, c3}};
+    void* tok = prof_begin(kProfAdjoint, s);
+    kMm[nt - 1](dim3((unsigned)blocks), s, X, n, d, U, r, Phi, T, grad_out, accumulate,
+                xr_flag, xr, (int)cb, dX);
+    const hipError_t e = hipGetLastError();
+    prof_end(tok, s);
+    return e;
+  }
   const AdjClass* cls = nullptr;
   for (const AdjClass& c : kAdj)
     if (r <= c.rmax) { cls = &c; break; }

@@ -430,6 +430,73 @@ def test_gradients_match_oracle(api, rng_mode):
 
 
 @pytest.mark.parametrize("rng_mode", RANGES)
+@pytest.mark.parametrize("n,m,d,r,eps,kind", [
+    (300, 250, 36, 100, 1.0, "normal"),     # 2 tiles + 4 coordinates, ragged k chunk
+    (129, 383, 8, 64, 0.5, "normal"),       # half of one tile
+    (260, 140, 128, 256, 1.0, "sphere"),    # 8 tiles in one workgroup
+    (200, 180, 784, 512, 10.0, "pixels"),   # 7 column blocks of 7 tiles
+])
+def test_gradients_match_oracle_wide_points(api, rng_mode, n, m, d, r, eps, kind):
+    """Point and weight gradients for d >= 8 (the matrix-core adjoint) vs
+    the oracle's formula on the row-scaled features at the same fixed
+    iteration count; row counts leave partial 128-row blocks, r leaves a
+    partial 32-feature chunk, d leaves partial 16-coordinate tiles."""
+    _say("wide gradients", rng_mode, n, m, d, r)
+    rng = np.random.default_rng(23 + d)
+    if kind == "pixels":
+        c = inputs.pixels(31, n=n, m=m, d=d)
+        X, Y, a, b = c.X, c.Y, c.a, c.b
+    elif kind == "sphere":
+        c = inputs.sphere(31, n=n, m=m, d=d)
+        X, Y, a, b = c.X, c.Y, c.a, c.b
+    else:
+        X = (0.4 * rng.standard_normal((n, d))).astype(np.float32)
+        Y = (0.4 * rng.standard_normal((m, d)) + 0.1).astype(np.float32)
+        a = inputs.dirichlet_weights(rng, n)
+        b = inputs.dirichlet_weights(rng, m)
+    q = oracle.lambert_q(inputs.max_norm(X, Y), eps, d)
+    U = inputs.gaussian_anchors(3, r, d, oracle.sigma2_from_q(q, eps))
+    out, st = api.divergence(dev(X), dev(Y), dev(a), dev(b), dev(U), eps, q,
+                             fixed_iter=200, range=rng_mode)
+    dX, da, dY, db = [host(t) for t in api.divergence_backward(st)]
+    rX, ra, rY, rb, div = oracle.divergence_grad_scaled(X, Y, a, b, U, eps, q,
+                                                        fixed_iter=200)
+    assert host(out)[0] == pytest.approx(div.value, rel=DIV_RTOL, abs=1e-7 * abs(div.w_xy))
+    for gg, rr in ((dX, rX), (da, ra), (dY, rY), (db, rb)):
+        rel = np.linalg.norm(gg - rr) / np.linalg.norm(rr)
+        assert rel <= GRAD_RTOL, rel
+        assert np.all(np.abs(gg - rr) <= GRAD_RTOL * np.abs(rr).max() * 10)
+
+
+@pytest.mark.parametrize("rng_mode", RANGES)
+def test_point_gradient_accumulates_single_terms(api, rng_mode):
+    """The single-term entry point with accumulation, for d >= 8: summing
+    the three weighted terms of dW_bar/dX one call at a time gives the
+    three-term result of the divergence backward."""
+    _say("single-term accumulate", rng_mode)
+    rng = np.random.default_rng(41)
+    n, m, d, r, eps = 270, 200, 20, 68, 1.0
+    X = (0.4 * rng.standard_normal((n, d))).astype(np.float32)
+    Y = (0.4 * rng.standard_normal((m, d)) + 0.1).astype(np.float32)
+    a = inputs.dirichlet_weights(rng, n)
+    b = inputs.dirichlet_weights(rng, m)
+    q = oracle.lambert_q(inputs.max_norm(X, Y), eps, d)
+    U = inputs.gaussian_anchors(4, r, d, oracle.sigma2_from_q(q, eps))
+    Xd, Ud = dev(X), dev(U)
+    out, st = api.divergence(Xd, dev(Y), dev(a), dev(b), Ud, eps, q, fixed_iter=150,
+                             range=rng_mode)
+    dX3 = host(api.divergence_backward(st, need=(True, False, False, False))[0])
+    u0, _, w0, _ = st.scalings(0)
+    u1, v1, w1, z1 = st.scalings(1)
+    acc = None
+    for p, g, cf in ((u0, w0, 1.0), (u1, w1, -0.5), (v1, z1, -0.5)):
+        acc = api.features_backward(Xd, Ud, st.phix, p, g, coef=cf, dX=acc,
+                                    accumulate=acc is not None, range=st.range)
+    got = host(acc)
+    assert np.linalg.norm(got - dX3) <= 1e-5 * np.linalg.norm(dX3)
+
+
+@pytest.mark.parametrize("rng_mode", RANGES)
 @pytest.mark.parametrize("n,m,d,r,eps", [(300, 250, 3, 256, 0.7), (500, 420, 2, 64, 0.5),
                                          (260, 300, 16, 100, 1.0)])
 def test_anchor_gradients_match_oracle(api, rng_mode, n, m, d, r, eps):
