@@ -223,17 +223,27 @@ def _time(torch, fn, reps=3):
 
 
 def time_extras(torch, api, X, Y, U, state, wl, q):
-    """Anchor gradient (one read of each feature matrix per 4 coordinates)
-    and arc-cosine features of X (r + 1 = 1024 columns), on this workload."""
+    """Anchor gradient and arc-cosine features of X (r + 1 columns), on this
+    workload.  For d < 8 the anchor gradient reads each feature matrix once
+    per 4 coordinates (HBM-bound); for d >= 8 (d % 4 == 0) it is the
+    product H^T Z on the matrix cores, 2 r d (n + m) flops."""
     n, m, d, r = wl["n"], wl["m"], wl["d"], wl["r"]
     ms_dU = _time(torch, lambda: api.divergence_backward_anchors(state))
-    bytes_dU = 4.0 * r * (n + m) * ((d + 3) // 4)
+    if d >= 8 and d % 4 == 0:
+        flops = 2.0 * r * d * (n + m)
+        dU_rec = {"ms": ms_dU, "flops": flops,
+                  "TFLOPs": flops / (ms_dU / 1e3) / 1e12,
+                  "frac_of_fp32_mfma_peak": flops / (ms_dU / 1e3) / 1e12 /
+                  MFMA_FP32_PEAK_TFLOPS}
+    else:
+        bytes_dU = 4.0 * r * (n + m) * ((d + 3) // 4)
+        dU_rec = {"ms": ms_dU, "feature_bytes_read": bytes_dU,
+                  "GBps": bytes_dU / (ms_dU / 1e3) / 1e9}
     U1 = U[: r - 1].contiguous()
     ms_arc = _time(torch, lambda: api.features_arccos(X, U1, 1, 1.5, 0.5))
     bytes_arc = 4.0 * n * r
     return {
-        "anchor_gradient": {"ms": ms_dU, "feature_bytes_read": bytes_dU,
-                            "GBps": bytes_dU / (ms_dU / 1e3) / 1e9},
+        "anchor_gradient": dU_rec,
         "arccos_features": {"ms": ms_arc, "bytes_written": bytes_arc,
                             "GBps": bytes_arc / (ms_arc / 1e3) / 1e9,
                             "s": 1, "r_plus_1": r},

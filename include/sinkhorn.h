@@ -344,7 +344,9 @@ int sinkhorn_divergence_backward(const sk_problem* p, const void* state,
  * combined as dW(x,y) - (dW(x,x) + dW(y,y)) / 2 and scaled by *grad_out (a
  * device float, or 1 if NULL).  dU: device r x d floats (overwritten).
  * ws: sinkhorn_divergence_backward_anchors_workspace_size bytes (partial
- * sums; the reduction is deterministic).  Errors: SK_EINVAL, SK_ENOMEM. */
+ * sums: about 2.2e4 r floats for d < 8, and for d >= 8 one r x d float
+ * block per slice of the points, at most 64 slices; the reduction is
+ * deterministic).  Errors: SK_EINVAL, SK_ENOMEM. */
 size_t sinkhorn_divergence_backward_anchors_workspace_size(const sk_problem* p);
 int sinkhorn_divergence_backward_anchors(const sk_problem* p, const void* state,
                                          const float* grad_out, float* dU,

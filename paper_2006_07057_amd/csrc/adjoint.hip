@@ -717,6 +717,250 @@ anchor_grad_final(const double* __restrict__ chunks, int r, int d, int dim0, int
   dU[(int64_t)k * d + dim0 + e] = (float)(go * sum);
 }
 
+// Matrix-core variant for d >= 8: A = sum over both sides of H^T Z, an
+// r x d product with the point rows as the contraction index.  A
+// workgroup owns 128 anchors (32 per wave) x 16 NT coordinates and one of
+// S slices of the rows of each side; per chunk of 32 rows it stages the
+// feature block (rows x 128 anchors), the point block (rows x tile) and the
+// rows' scalings in double-buffered LDS, one chunk ahead in registers.
+// Each lane forms h_ik for its A fragment (anchors l16 and l16 + 16 of its
+// wave, rows 8q .. 8q+7) with the anchor factors c_t g^t_k held in
+// registers.  Slices write float32 partial tiles; the final kernel adds
+// them in float64 in slice order.
+constexpr int kAmAnchors = 128;
+constexpr int kAmRows = 32;
+constexpr int kAmPadA = kAmAnchors + 4;
+
+int anchor_mm_slices(int r, int d, int64_t rows) {
+  const int nt = mm_tiles(d);
+  const int64_t tiles = (int64_t)((r + kAmAnchors - 1) / kAmAnchors) *
+                        ((d + 16 * nt - 1) / (16 * nt));
+  int64_t s = (2048 + tiles - 1) / tiles;
+  if (s > 64) s = 64;
+  if (s > rows / 1024) s = rows / 1024;
+  return s < 1 ? 1 : (int)s;
+}
+
+template <int NT>
+__global__ void __launch_bounds__(kBlock)
+anchor_grad_mfma(AnchorSide SX, AnchorSide SY, int r, int d, int slices, int col_blocks,
+                 const int32_t* __restrict__ xr_flag, float* __restrict__ part) {
+  constexpr int BN = 16 * NT;
+  constexpr int PB = BN + 4;
+  constexpr int BF4 = kAmRows * BN / 4;
+  constexpr int BPER = (BF4 + kBlock - 1) / kBlock;
+  __shared__ __align__(16) float sA[2][kAmRows * kAmPadA];
+  __shared__ __align__(16) float sB[2][kAmRows * PB];
+  __shared__ __align__(16) float sP[2][6 * kAmRows];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int q = lane >> 4;
+  const int l16 = lane & 15;
+  const bool xr = xr_flag && *xr_flag != 0;
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  const int L = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int ablocks = (r + kAmAnchors - 1) / kAmAnchors;
+  const int cbk = L % col_blocks;
+  const int ab = (L / col_blocks) % ablocks;
+  const int sl = L / (col_blocks * ablocks);
+  const int k0 = ab * kAmAnchors;
+  const int col0 = cbk * BN;
+
+  f4v acc[2][NT];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[rt][t] = f4v{0.f, 0.f, 0.f, 0.f};
+
+  // staging: feature block rows st_row (0..31), float4 st_f4 (0..31) of
+  // the 128 anchors; tid < 192 also stages one row scaling entry
+  const int st_f4 = tid & 31;
+  const int st_row = tid >> 5;   // 0..7, rows st_row + 8h
+  auto run_side = [&](const AnchorSide& S) {
+    const int64_t lo = S.n * sl / slices, hi = S.n * (sl + 1) / slices;
+    const int nchunks = (int)((hi - lo + kAmRows - 1) / kAmRows);
+    if (nchunks == 0) return;
+    // anchor factors of the lane's two A anchors
+    float ge[2][3], gm[2][3];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const int k = k0 + wave * 32 + 16 * rt + l16;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const bool ok = k < r;
+        ge[rt][t] = xr ? (ok ? S.g[t][k] : -1.0e30f) : 0.f;
+        gm[rt][t] = ok ? S.c[t] * (xr ? S.g[t][r + k] : S.g[t][k]) : 0.f;
+      }
+    }
+    f4v ra[4], rb[BPER];
+    float rp = 0.f;
+    auto gload = [&](int kc) {
+      const int64_t i0 = lo + (int64_t)kc * kAmRows;
+      const int k = k0 + 4 * st_f4;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int64_t i = i0 + st_row + 8 * h;
+        ra[h] = f4v{0.f, 0.f, 0.f, 0.f};
+        if (i < hi && k < r) ra[h] = *reinterpret_cast<const f4v*>(S.P + i * (int64_t)r + k);
+      }
+#pragma unroll
+      for (int j = 0; j < BPER; ++j) {
+        const int idx = tid + kBlock * j;
+        const int rr = idx / (BN / 4), c4 = idx % (BN / 4);
+        const int64_t i = i0 + rr;
+        const int dim = col0 + 4 * c4;
+        rb[j] = f4v{0.f, 0.f, 0.f, 0.f};
+        if (idx < BF4 && i < hi && dim < d)
+          rb[j] = *reinterpret_cast<const f4v*>(S.Z + i * (int64_t)d + dim);
+      }
+      if (tid < 6 * kAmRows) {
+        // slot s: linear p_s (s < 3); extended range E(p_t) (s = 2t), M(p_t) (s = 2t + 1)
+        const int s = tid / kAmRows;
+        const int64_t i = i0 + tid % kAmRows;
+        const int t = xr ? s >> 1 : s;
+        const bool mant = xr && (s & 1);
+        rp = xr ? (mant ? 0.f : -1.0e30f) : 0.f;
+        if (t < 3 && i < hi) rp = S.p[t][mant ? S.n + i : i];
+      }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int h = 0; h < 4; ++h)
+        *reinterpret_cast<f4v*>(&sA[buf][(st_row + 8 * h) * kAmPadA + 4 * st_f4]) = ra[h];
+#pragma unroll
+      for (int j = 0; j < BPER; ++j) {
+        const int idx = tid + kBlock * j;
+        if (idx < BF4) {
+          const int rr = idx / (BN / 4), c4 = idx % (BN / 4);
+          *reinterpret_cast<f4v*>(&sB[buf][rr * PB + 4 * c4]) = rb[j];
+        }
+      }
+      if (tid < 6 * kAmRows) sP[buf][tid] = rp;
+    };
+
+    __syncthreads();   // the previous side's last readers are done
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int kc = 0; kc < nchunks; ++kc) {
+      const int buf = kc & 1;
+      if (kc + 1 < nchunks) gload(kc + 1);
+      float hv[2][8];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) hv[rt][e] = 0.f;
+      if (xr) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const f4v e0 = *reinterpret_cast<const f4v*>(&sP[buf][(2 * t) * kAmRows + 8 * q]);
+          const f4v e1 = *reinterpret_cast<const f4v*>(&sP[buf][(2 * t) * kAmRows + 8 * q + 4]);
+          const f4v m0 = *reinterpret_cast<const f4v*>(&sP[buf][(2 * t + 1) * kAmRows + 8 * q]);
+          const f4v m1 = *reinterpret_cast<const f4v*>(&sP[buf][(2 * t + 1) * kAmRows + 8 * q + 4]);
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt) {
+            const float* A = &sA[buf][(8 * q) * kAmPadA + wave * 32 + 16 * rt + l16];
+            const float get = ge[rt][t], gmt = gm[rt][t];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              hv[rt][e] = fmaf(gmt * m0[e],
+                               __builtin_amdgcn_exp2f(A[e * kAmPadA] + (e0[e] + get)),
+                               hv[rt][e]);
+              hv[rt][4 + e] = fmaf(gmt * m1[e],
+                                   __builtin_amdgcn_exp2f(A[(4 + e) * kAmPadA] + (e1[e] + get)),
+                                   hv[rt][4 + e]);
+            }
+          }
+        }
+      } else {
+        f4v p0[3], p1[3];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          p0[t] = *reinterpret_cast<const f4v*>(&sP[buf][t * kAmRows + 8 * q]);
+          p1[t] = *reinterpret_cast<const f4v*>(&sP[buf][t * kAmRows + 8 * q + 4]);
+        }
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+          const float* A = &sA[buf][(8 * q) * kAmPadA + wave * 32 + 16 * rt + l16];
+          const float g1 = gm[rt][0], g2 = gm[rt][1], g3 = gm[rt][2];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            hv[rt][e] = A[e * kAmPadA] * (g1 * p0[0][e] + g2 * p0[1][e] + g3 * p0[2][e]);
+            hv[rt][4 + e] =
+                A[(4 + e) * kAmPadA] * (g1 * p1[0][e] + g2 * p1[1][e] + g3 * p1[2][e]);
+          }
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float bv[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bv[t] = sB[buf][(8 * q + e) * PB + 16 * t + l16];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            acc[rt][t] =
+                __builtin_amdgcn_mfma_f32_16x16x4f32(hv[rt][e], bv[t], acc[rt][t], 0, 0, 0);
+      }
+      if (kc + 1 < nchunks) lstore(buf ^ 1);
+      __syncthreads();
+    }
+  };
+  run_side(SX);
+  run_side(SY);
+  // acc[rt][t][v]: anchor wave*32 + 16 rt + 4q + v, coordinate 16 t + l16
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = k0 + wave * 32 + 16 * rt + 4 * q + v;
+      if (k >= r) continue;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int dim = col0 + 16 * t + l16;
+        if (dim < d) part[((int64_t)sl * r + k) * d + dim] = acc[rt][t][v];
+      }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+anchor_grad_mm_final(const float* __restrict__ part, int slices, int r, int d,
+                     const float* __restrict__ U, double ucoef,
+                     const float* zxy, const float* wxy, const float* zxx,
+                     const float* wxx, const float* zyy, const float* wyy,
+                     const int32_t* __restrict__ xr_flag,
+                     const float* __restrict__ grad_out, float* __restrict__ dU) {
+  const bool xr = xr_flag && *xr_flag != 0;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)r * d;
+  if (idx >= total) return;
+  const int k = (int)(idx / d);
+  double sum = 0.0;
+  for (int s = 0; s < slices; ++s) sum += (double)part[(int64_t)s * total + idx];
+  const double m = rvec(zxy, r, k, xr) * rvec(wxy, r, k, xr) -
+                   0.5 * (rvec(zxx, r, k, xr) * rvec(wxx, r, k, xr) +
+                          rvec(zyy, r, k, xr) * rvec(wyy, r, k, xr));
+  sum += ucoef * m * (double)U[idx];
+  const double go = grad_out ? (double)*grad_out : 1.0;
+  dU[idx] = (float)(go * sum);
+}
+
+typedef void (*AmLaunch)(dim3, hipStream_t, const AnchorSide&, const AnchorSide&, int, int,
+                         int, int, const int32_t*, float*);
+
+template <int NT>
+void launch_am(dim3 grid, hipStream_t s, const AnchorSide& SX, const AnchorSide& SY, int r,
+               int d, int slices, int cb, const int32_t* xf, float* part) {
+  hipLaunchKernelGGL((anchor_grad_mfma<NT>), grid, dim3(kBlock), 0, s, SX, SY, r, d, slices,
+                     cb, xf, part);
+}
+
+const AmLaunch kAm[8] = {&launch_am<1>, &launch_am<2>, &launch_am<3>, &launch_am<4>,
+                         &launch_am<5>, &launch_am<6>, &launch_am<7>, &launch_am<8>};
+
 }  // namespace
 
 hipError_t launch_features_backward(const float* X, int64_t n, int d,
@@ -778,7 +1022,9 @@ hipError_t launch_weight_grad(const float* u1, const float* u2,
   return hipGetLastError();
 }
 
-size_t anchor_grad_scratch_floats(int r) {
+size_t anchor_grad_scratch_floats(int r, int d, int64_t n, int64_t m) {
+  // matrix cores: one float32 partial r x d result per row slice
+  if (use_mm(d)) return (size_t)anchor_mm_slices(r, d, n < m ? n : m) * (size_t)r * d;
   // two sides of workgroup partials, then the float64 chunk sums
   return (size_t)2 * kAnchorBlocks * (size_t)r * kAnchorDch +
          (size_t)2 * kAnchorChunks * (size_t)r * kAnchorDch;
@@ -806,6 +1052,21 @@ hipError_t launch_anchor_grad(const float* X, int64_t n, const float* Y, int64_t
   AnchorSide SX{Phix, X, {u[0], u[1], v[1]}, {w[0], w[1], z[1]}, {-4.f, 2.f, 2.f}, n};
   AnchorSide SY{Phiy, Y, {v[0], u[2], v[2]}, {z[0], w[2], z[2]}, {-4.f, 2.f, 2.f}, m};
   const double ucoef = 4.0 * (2.0 - 1.0 / q);
+  if (use_mm(d)) {
+    const int nt = mm_tiles(d);
+    const int slices = anchor_mm_slices(r, d, n < m ? n : m);
+    const int cb = (d + 16 * nt - 1) / (16 * nt);
+    const int64_t blocks = (int64_t)slices * ((r + kAmAnchors - 1) / kAmAnchors) * cb;
+    const int64_t total = (int64_t)r * d;
+    void* tok = prof_begin(kProfAdjoint, s);
+    kAm[nt - 1](dim3((unsigned)blocks), s, SX, SY, r, d, slices, cb, xr_flag, scratch);
+    hipLaunchKernelGGL(anchor_grad_mm_final, dim3((unsigned)((total + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, scratch, slices, r, d, U, ucoef, z[0], w[0], z[1],
+                       w[1], z[2], w[2], xr_flag, grad_out, dU);
+    const hipError_t e = hipGetLastError();
+    prof_end(tok, s);
+    return e;
+  }
   void* tok = prof_begin(kProfAdjoint, s);
   for (int dim0 = 0; dim0 < d; dim0 += kAnchorDch) {
     const int dch = d - dim0 < kAnchorDch ? d - dim0 : kAnchorDch;

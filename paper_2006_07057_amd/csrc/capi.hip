@@ -772,7 +772,7 @@ int sinkhorn_divergence_backward(const sk_problem* p, const void* state,
 
 size_t sinkhorn_divergence_backward_anchors_workspace_size(const sk_problem* p) {
   if (check_problem(p) != SK_OK) return 0;
-  return anchor_grad_scratch_floats((int)p->r) * sizeof(float);
+  return anchor_grad_scratch_floats((int)p->r, (int)p->d, p->n, p->m) * sizeof(float);
 }
 
 int sinkhorn_divergence_backward_anchors(const sk_problem* p, const void* state,
@@ -781,7 +781,8 @@ int sinkhorn_divergence_backward_anchors(const sk_problem* p, const void* state,
   int rc = check_problem(p);
   if (rc) return rc;
   if (!state || !dU || !ws) return SK_EINVAL;
-  if (ws_bytes < anchor_grad_scratch_floats((int)p->r) * sizeof(float)) return SK_ENOMEM;
+  if (ws_bytes < anchor_grad_scratch_floats((int)p->r, (int)p->d, p->n, p->m) * sizeof(float))
+    return SK_ENOMEM;
   sk_state_layout L;
   layout_of(p->n, p->m, p->r, &L);
   const float* u[3];

@@ -119,7 +119,7 @@ hipError_t launch_features_backward(const float* X, int64_t n, int d,
 hipError_t launch_features_arccos(const float* X, int64_t n, int d, const float* U,
                                   int r, int s_exp, double sigma, double kappa,
                                   float* Phi, float* logscale, hipStream_t s);
-size_t anchor_grad_scratch_floats(int r);
+size_t anchor_grad_scratch_floats(int r, int d, int64_t n, int64_t m);
 hipError_t launch_anchor_grad(const float* X, int64_t n, const float* Y, int64_t m,
                               int d, const float* U, int r, double q,
                               const float* Phix, const float* Phiy,

@@ -521,6 +521,34 @@ def test_anchor_gradients_match_oracle(api, rng_mode, n, m, d, r, eps):
     assert np.all(np.abs(dU - rU) <= GRAD_RTOL * np.abs(rU).max() * 10)
 
 
+@pytest.mark.parametrize("rng_mode", RANGES)
+@pytest.mark.parametrize("n,m,d,r,eps", [
+    (300, 250, 36, 132, 1.0),      # partial anchor block and coordinate tile
+    (4100, 3100, 12, 64, 1.0),     # three row slices, ragged rows
+    (260, 140, 128, 256, 0.5),     # 8 coordinate tiles, two anchor blocks
+    (150, 170, 200, 68, 2.0),      # 13 tiles: 2 column blocks of 7
+])
+def test_anchor_gradients_wide_points(api, rng_mode, n, m, d, r, eps):
+    """Anchor gradient for d >= 8 (the matrix-core product H^T Z over row
+    slices) vs the oracle's closed form at the same fixed iteration count."""
+    _say("wide anchor gradients", rng_mode, n, m, d, r)
+    rng = np.random.default_rng(29 + d)
+    X = (0.4 * rng.standard_normal((n, d))).astype(np.float32)
+    Y = (0.4 * rng.standard_normal((m, d)) + 0.1).astype(np.float32)
+    a = inputs.dirichlet_weights(rng, n)
+    b = inputs.dirichlet_weights(rng, m)
+    q = oracle.lambert_q(inputs.max_norm(X, Y), eps, d)
+    U = inputs.gaussian_anchors(5, r, d, oracle.sigma2_from_q(q, eps))
+    out, st = api.divergence(dev(X), dev(Y), dev(a), dev(b), dev(U), eps, q,
+                             fixed_iter=150, range=rng_mode)
+    dU = host(api.divergence_backward_anchors(st))
+    rU, div = oracle.divergence_grad_anchors(X, Y, a, b, U, eps, q, fixed_iter=150)
+    assert host(out)[0] == pytest.approx(div.value, rel=DIV_RTOL, abs=1e-7 * abs(div.w_xy))
+    rel = np.linalg.norm(dU - rU) / np.linalg.norm(rU)
+    assert rel <= GRAD_RTOL, rel
+    assert np.all(np.abs(dU - rU) <= GRAD_RTOL * np.abs(rU).max() * 10)
+
+
 def test_anchor_gradient_autograd(api):
     _say("anchor autograd")
     c, U, eps, q = _divergence_inputs("gauss2d", n=300, m=280)
