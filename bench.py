@@ -242,12 +242,15 @@ def time_extras(torch, api, X, Y, U, state, wl, q):
     U1 = U[: r - 1].contiguous()
     ms_arc = _time(torch, lambda: api.features_arccos(X, U1, 1, 1.5, 0.5))
     bytes_arc = 4.0 * n * r
-    return {
-        "anchor_gradient": dU_rec,
-        "arccos_features": {"ms": ms_arc, "bytes_written": bytes_arc,
-                            "GBps": bytes_arc / (ms_arc / 1e3) / 1e9,
-                            "s": 1, "r_plus_1": r},
-    }
+    arc_rec = {"ms": ms_arc, "bytes_written": bytes_arc,
+               "GBps": bytes_arc / (ms_arc / 1e3) / 1e9, "s": 1, "r_plus_1": r}
+    if d >= 8 and d % 4 == 0:
+        # projections u_k . x on the matrix cores: 2 d (r - 1) n flops
+        flops = 2.0 * d * (r - 1) * n
+        arc_rec.update({"flops": flops, "TFLOPs": flops / (ms_arc / 1e3) / 1e12,
+                        "frac_of_fp32_mfma_peak": flops / (ms_arc / 1e3) / 1e12 /
+                        MFMA_FP32_PEAK_TFLOPS})
+    return {"anchor_gradient": dU_rec, "arccos_features": arc_rec}
 
 
 def run_features_only(args, wl, torch, api, X, Y, U, q):

@@ -228,14 +228,37 @@ anchor_cval_kernel(const float* __restrict__ U, int r, int d, float c0, float cu
   if (lane == 0) g_anchor_cval[k] = fmaf(cu, (float)un, c0);
 }
 
+// Arc-cosine variant of the anchor terms, c0 + cu ||u_k||^2 formed in
+// float64 and rounded once.
+__global__ void __launch_bounds__(kBlock)
+anchor_cterm_kernel(const float* __restrict__ U, int r, int d, double c0, double cu) {
+  const int k = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (k >= r) return;   // whole waves leave together
+  double un = 0.0;
+  for (int e = lane; e < d; e += 64) {
+    const double v = U[(int64_t)k * d + e];
+    un += v * v;
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) un += __shfl_xor(un, off, 64);
+  if (lane == 0) g_anchor_cval[k] = (float)(c0 + cu * un);
+}
+
 constexpr int kMfmaTilePad = 68;  // floats per row of the LDS transpose tile
 
-template <bool LOG2>
+// MODE 0: Gaussian features, linear output; 1: Gaussian, log2 output;
+// 2: arc-cosine features, linear output with the constant column r
+// (width r + 1): l_k = c_k + s log(u_k.x) for u_k.x > 0, else -inf.
+template <int MODE>
 __global__ void __launch_bounds__(kBlock)
 features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
                      const float* __restrict__ U, int r,
-                     float scale, float neg2e, float* __restrict__ Phi,
-                     float* __restrict__ logscale) {
+                     float scale, float neg2e, int s_exp, float lk,
+                     float* __restrict__ Phi, float* __restrict__ logscale) {
+  constexpr bool LOG2 = MODE == 1;
+  const int W = MODE == 2 ? r + 1 : r;   // output columns (row stride)
+  const bool w4 = (W & 3) == 0;
   __shared__ __align__(16) float sA[2][kMfmaRows * kMfmaPad];
   __shared__ __align__(16) float sB[2][kMfmaCols * kMfmaPad];
   __shared__ float s_xn[kMfmaRows];
@@ -286,7 +309,7 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
   const int prow = lane >> 4;
   const int pcol = 4 * (lane & 15);
 
-  for (int cb = 0; cb < r; cb += kMfmaCols) {
+  for (int cb = 0; cb < W; cb += kMfmaCols) {
     f4v acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
@@ -329,8 +352,16 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
       const float cval = col < r ? g_anchor_cval[col] : 0.f;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const float Dv = fmaf(scale, acc[t][v], cval);
-        if (col < r) mrow[v] = fmaxf(mrow[v], Dv);
+        float Dv;
+        if (MODE == 2) {
+          const float dot = acc[t][v];
+          Dv = col >= r ? lk
+               : dot > 0.f ? (s_exp == 0 ? cval : fmaf((float)s_exp, logf(dot), cval))
+                           : -INFINITY;
+        } else {
+          Dv = fmaf(scale, acc[t][v], cval);
+        }
+        if (col < W) mrow[v] = fmaxf(mrow[v], Dv);
         tile[(4 * q + v) * kMfmaTilePad + 16 * t + l16] = Dv;
       }
     }
@@ -342,7 +373,15 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
       const int64_t row = row_base + tr;
       const int col = cb + pcol;
       const f4v val = *reinterpret_cast<const f4v*>(&tile[tr * kMfmaTilePad + pcol]);
-      if (row < n && col < r) *reinterpret_cast<f4v*>(Phi + row * (int64_t)r + col) = val;
+      if (row < n && col < W) {
+        if (w4) {
+          *reinterpret_cast<f4v*>(Phi + row * (int64_t)W + col) = val;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (col + e < W) Phi[row * (int64_t)W + col + e] = val[e];
+        }
+      }
     }
     __builtin_amdgcn_wave_barrier();      // the tile is read before it is rewritten
   }
@@ -360,27 +399,34 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
   float pmax[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) pmax[j] = s_max[wave * 16 + prow + 4 * j];
-  for (int cb = 0; cb < r; cb += kMfmaCols) {
+  for (int cb = 0; cb < W; cb += kMfmaCols) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t row = row_base + prow + 4 * j;
       const int col = cb + pcol;
-      if (row >= n || col >= r) continue;
-      f4v* p = reinterpret_cast<f4v*>(Phi + row * (int64_t)r + col);
-      f4v x = *p;
+      if (row >= n || col >= W) continue;
+      float* p = Phi + row * (int64_t)W + col;
+      if (w4) {
+        f4v x = *reinterpret_cast<f4v*>(p);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float y = x[e] - pmax[j];
-        x[e] = LOG2 ? y * kLog2e : expf(y);
+        for (int e = 0; e < 4; ++e) {
+          const float y = x[e] - pmax[j];
+          x[e] = LOG2 ? y * kLog2e : expf(y);
+        }
+        *reinterpret_cast<f4v*>(p) = x;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (col + e < W) p[e] = expf(p[e] - pmax[j]);
       }
-      *p = x;
     }
   }
   if (l16 == 0) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t row = row_base + 4 * q + v;
-      if (row < n) logscale[row] = fmaf(neg2e, s_xn[wave * 16 + 4 * q + v], mrow[v]);
+      if (row < n)
+        logscale[row] = MODE == 2 ? mrow[v] : fmaf(neg2e, s_xn[wave * 16 + 4 * q + v], mrow[v]);
     }
   }
 }
@@ -401,11 +447,11 @@ hipError_t launch_mfma(const FeatDesc& D, hipStream_t s) {
   const hipError_t e0 = hipGetLastError();
   if (e0 != hipSuccess) return e0;
   if (D.log2_out)
-    hipLaunchKernelGGL(features_mfma_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), 0,
-                       s, D.X, D.n, D.d, D.U, D.r, scale, neg2e, D.Phi, D.s);
+    hipLaunchKernelGGL(features_mfma_kernel<1>, dim3((unsigned)blocks), dim3(kBlock), 0,
+                       s, D.X, D.n, D.d, D.U, D.r, scale, neg2e, 0, 0.f, D.Phi, D.s);
   else
-    hipLaunchKernelGGL(features_mfma_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), 0,
-                       s, D.X, D.n, D.d, D.U, D.r, scale, neg2e, D.Phi, D.s);
+    hipLaunchKernelGGL(features_mfma_kernel<0>, dim3((unsigned)blocks), dim3(kBlock), 0,
+                       s, D.X, D.n, D.d, D.U, D.r, scale, neg2e, 0, 0.f, D.Phi, D.s);
   return hipGetLastError();
 }
 
@@ -669,6 +715,22 @@ hipError_t launch_features_arccos(const float* X, int64_t n, int d, const float*
   const float c0 = (float)(-0.5 * log((double)r) + 0.5 * d * log(sigma) + 0.5 * log(2.0));
   const float cu = (float)(-0.25 * (1.0 - 1.0 / (sigma * sigma)));
   const float lk = (float)(0.5 * log(kappa));
+  if (use_mfma(d)) {
+    // projections u_k.x on the matrix cores (r + 1 output columns)
+    const int64_t blocks = (n + kMfmaRows - 1) / kMfmaRows;
+    if (blocks > 0x7fffffff || r + 1 > SK_MAX_R) return hipErrorInvalidValue;
+    void* tok = prof_begin(kProfFeatures, s);
+    hipLaunchKernelGGL(anchor_cterm_kernel, dim3((r + kWaves - 1) / kWaves), dim3(kBlock), 0,
+                       s, U, r, d, (double)c0, (double)cu);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(features_mfma_kernel<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                         X, n, d, U, r, 1.0f, 0.f, s_exp, lk, Phi, logscale);
+      e = hipGetLastError();
+    }
+    prof_end(tok, s);
+    return e;
+  }
   int64_t grid = (int64_t)device_cus() * 8;
   const int64_t need = (n + kWaves - 1) / kWaves;
   if (grid > need) grid = need;

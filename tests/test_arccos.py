@@ -33,7 +33,11 @@ def _data(seed, n, m, d, r, sigma):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("s", [0, 1, 2])
-@pytest.mark.parametrize("d,r", [(3, 127), (16, 255), (2, 1023)])
+@pytest.mark.parametrize("d,r", [(3, 127), (16, 255), (2, 1023),
+                                 # matrix-core projections (d >= 8, d % 4 == 0):
+                                 # r + 1 = 101 columns (unaligned rows), pixel width,
+                                 # 16 column blocks
+                                 (36, 100), (784, 127), (128, 1023)])
 def test_arccos_features_match_oracle(s, d, r):
     import torch
     from paper_2006_07057_amd import api
@@ -72,11 +76,12 @@ def test_arccos_features_match_oracle(s, d, r):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("s", [1, 2])
-def test_arccos_divergence_matches_oracle(s):
+@pytest.mark.parametrize("d", [3, 16])
+def test_arccos_divergence_matches_oracle(s, d):
     import torch
     from paper_2006_07057_amd import api
     sigma, kappa, eps = 1.4, 0.5, 0.5
-    n, m, d, r = 300, 260, 3, 127
+    n, m, r = 300, 260, 127
     X, Y, U = _data(10 + s, n, m, d, r, sigma)
     rng = np.random.default_rng(3)
     a = inputs.dirichlet_weights(rng, n)
