@@ -50,7 +50,8 @@ features_backward_kernel(const float* __restrict__ X, int64_t n, int d,
                          const float* __restrict__ grad_out, int accumulate,
                          const int32_t* __restrict__ xr_flag, int xr_host,
                          float* __restrict__ dX) {
-  __shared__ float Ut[kAdjUtFloats];
+  // transposed anchors (dynamic: d * rp floats when they fit, else none)
+  extern __shared__ __align__(16) float Ut[];
   // r-vectors: linear g_t at gv[t*R..], extended range E at gv[2t*R..],
   // M at gv[(2t+1)*R..]
   __shared__ float4 gv4[6 * G * C];
@@ -191,19 +192,19 @@ features_backward_kernel(const float* __restrict__ X, int64_t n, int d,
   }
 }
 
-typedef void (*AdjLaunch)(dim3, hipStream_t, const float*, int64_t, int,
+typedef void (*AdjLaunch)(dim3, size_t, hipStream_t, const float*, int64_t, int,
                           const float*, int, const float*, const float*,
                           const float*, float, const float*, const float*,
                           float, const float*, const float*, float,
                           const float*, int, const int32_t*, int, float*);
 
 template <int G, int C>
-void launch_adj(dim3 grid, hipStream_t s, const float* X, int64_t n, int d,
+void launch_adj(dim3 grid, size_t shmem, hipStream_t s, const float* X, int64_t n, int d,
                 const float* U, int r, const float* Phi, const float* p1,
                 const float* g1, float c1, const float* p2, const float* g2,
                 float c2, const float* p3, const float* g3, float c3,
                 const float* go, int acc, const int32_t* xf, int xh, float* dX) {
-  hipLaunchKernelGGL((features_backward_kernel<G, C>), grid, dim3(kBlock), 0, s,
+  hipLaunchKernelGGL((features_backward_kernel<G, C>), grid, dim3(kBlock), shmem, s,
                      X, n, d, U, r, Phi, p1, g1, c1, p2, g2, c2, p3, g3, c3, go,
                      acc, xf, xh, dX);
 }
@@ -996,8 +997,11 @@ hipError_t launch_features_backward(const float* X, int64_t n, int d,
   int64_t grid = (n + rows_per_block - 1) / rows_per_block;
   if (grid > (int64_t)cus * 16) grid = (int64_t)cus * 16;
   if (grid < 1) grid = 1;
+  // the kernel stages U^T in LDS exactly when d * rp <= kAdjUtFloats
+  const int64_t rp = (r + 3) & ~3;
+  const size_t shmem = (int64_t)d * rp <= kAdjUtFloats ? (size_t)d * rp * sizeof(float) : 0;
   void* tok = prof_begin(kProfAdjoint, s);
-  cls->launch(dim3((unsigned)grid), s, X, n, d, U, r, Phi, p1, g1, c1, p2, g2,
+  cls->launch(dim3((unsigned)grid), shmem, s, X, n, d, U, r, Phi, p1, g1, c1, p2, g2,
               c2, p3, g3, c3, grad_out, accumulate, xr_flag, xr, dX);
   const hipError_t e = hipGetLastError();
   prof_end(tok, s);

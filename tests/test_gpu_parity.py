@@ -435,12 +435,15 @@ def test_gradients_match_oracle(api, rng_mode):
     (129, 383, 8, 64, 0.5, "normal"),       # half of one tile
     (260, 140, 128, 256, 1.0, "sphere"),    # 8 tiles in one workgroup
     (200, 180, 784, 512, 10.0, "pixels"),   # 7 column blocks of 7 tiles
+    (130, 150, 6, 4096, 1.0, "normal"),     # per-row kernel, anchors not in LDS
 ])
 def test_gradients_match_oracle_wide_points(api, rng_mode, n, m, d, r, eps, kind):
     """Point and weight gradients for d >= 8 (the matrix-core adjoint) vs
     the oracle's formula on the row-scaled features at the same fixed
     iteration count; row counts leave partial 128-row blocks, r leaves a
-    partial 32-feature chunk, d leaves partial 16-coordinate tiles."""
+    partial 32-feature chunk, d leaves partial 16-coordinate tiles.  d = 6
+    (not a multiple of 4) with r = 4096 takes the per-row kernel with the
+    anchors read from memory (d r exceeds its LDS staging)."""
     _say("wide gradients", rng_mode, n, m, d, r)
     rng = np.random.default_rng(23 + d)
     if kind == "pixels":
