@@ -16,6 +16,7 @@ oracle on a bounded sample of the same workload on the host cores.
 
     python bench.py [--steps K] [--warmup W] [--workload gmm3d_1m]
     python bench.py --workload gauss2d_1k   # + plain dense Sinkhorn comparator
+    python bench.py --workload sphere128_8k # OT-GAN-shaped forward + gradients
     python bench.py --workload stream       # serving: Poisson request stream
     python bench.py --workload gauss2d_1m --accelerated   # accelerated solves
 """
@@ -42,9 +43,14 @@ WORKLOADS = {
     "gmm3d_1m": dict(kind="gmm3d", n=1_000_000, m=1_000_000, d=3, r=1024,
                      eps=0.1, tol=1e-6, max_iter=2000, fixed_iter=0),
     # pixel-like vectors U[0,1]^784, n = m = 65536, r = 4096, eps = 10,
-    # Lambert q: the matrix-core feature map dominates
+    # Lambert q: matrix-core feature map and adjoint beside a short solve
     "pixels_64k": dict(kind="pixels", n=65536, m=65536, d=784, r=4096, eps=10.0,
                        tol=1e-6, max_iter=2000, fixed_iter=0),
+    # the differentiation workload shaped like the OT-GAN experiment:
+    # n = m = 8192 unit vectors in R^128, r = 2048, eps = 1, Lambert q,
+    # stop at L1 marginal error < 1e-7; a step is forward + gradients
+    "sphere128_8k": dict(kind="sphere", n=8192, m=8192, d=128, r=2048, eps=1.0,
+                         tol=1e-7, max_iter=2000, fixed_iter=0),
     # x ~ N(0, I_2), y ~ N(1.5*1, I_2), n = m = 1000, r = 128, sigma^2 = 1,
     # 200 fixed iterations
     "gauss2d_1k": dict(kind="gauss2d", n=1000, m=1000, d=2, r=128, eps=0.5,
@@ -91,8 +97,9 @@ def plain_sinkhorn(torch, api, X, Y, a, b, U, wl, q, reps=5):
 
 
 def make_inputs(wl, seed, api, inputs):
-    if wl["kind"] in ("gmm3d", "pixels"):
-        gen = inputs.gmm3d if wl["kind"] == "gmm3d" else inputs.pixels
+    if wl["kind"] in ("gmm3d", "pixels", "sphere"):
+        gen = {"gmm3d": inputs.gmm3d, "pixels": inputs.pixels,
+               "sphere": inputs.sphere}[wl["kind"]]
         c = gen(seed, n=wl["n"], m=wl["m"], d=wl["d"])
         R = inputs.max_norm(c.X, c.Y)
         q = api.gaussian_q(R, wl["eps"], wl["d"])
@@ -698,7 +705,9 @@ def main(argv=None):
             "adjoint": adj_ms / max(args.steps, 1),
         },
         "plain_sinkhorn": (f"not run at this size: the dense n x m kernel "
-                           f"would need {4.0 * n * m:.1e} bytes"),
+                           f"would need {4.0 * n * m:.1e} bytes"
+                           if n * m > 1e8 else
+                           "not run: the comparator runs fixed iteration counts only"),
     }
     if n * m <= 1e8 and wl["fixed_iter"] > 0:
         print("[bench] plain dense Sinkhorn comparator", file=sys.stderr, flush=True)

@@ -738,7 +738,7 @@ int anchor_mm_slices(int r, int d, int64_t rows) {
                         ((d + 16 * nt - 1) / (16 * nt));
   int64_t s = (2048 + tiles - 1) / tiles;
   if (s > 64) s = 64;
-  if (s > rows / 1024) s = rows / 1024;
+  if (s > rows / 256) s = rows / 256;
   return s < 1 ? 1 : (int)s;
 }
 
@@ -973,10 +973,17 @@ hipError_t launch_features_backward(const float* X, int64_t n, int d,
                                     const int32_t* xr_flag, int xr, float* dX,
                                     hipStream_t s) {
   if (r % 4 != 0) return hipErrorInvalidValue;
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (use_mm(d)) {
-    const int nt = mm_tiles(d);
+    // few row blocks (small n): narrower coordinate tiles until every CU
+    // has a workgroup (each halving re-reads the feature rows once more)
+    const int64_t row_blocks = (n + kMmRows - 1) / kMmRows;
+    int nt = mm_tiles(d);
+    while (nt > 1 && row_blocks * ((d + 16 * nt - 1) / (16 * nt)) < cus) nt = (nt + 1) / 2;
     const int64_t cb = (d + 16 * nt - 1) / (16 * nt);
-    const int64_t blocks = ((n + kMmRows - 1) / kMmRows) * cb;
+    const int64_t blocks = row_blocks * cb;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     const AdjTerms T{{p1, p2, p3}, {g1, g2, g3}, {c1, c2, c3}};
     void* tok = prof_begin(kProfAdjoint, s);
@@ -990,9 +997,6 @@ hipError_t launch_features_backward(const float* X, int64_t n, int d,
   for (const AdjClass& c : kAdj)
     if (r <= c.rmax) { cls = &c; break; }
   if (!cls) return hipErrorInvalidValue;
-  int dev = 0, cus = 256;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const int64_t rows_per_block = (int64_t)kWaves * cls->rpw;
   int64_t grid = (n + rows_per_block - 1) / rows_per_block;
   if (grid > (int64_t)cus * 16) grid = (int64_t)cus * 16;

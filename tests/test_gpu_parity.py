@@ -527,7 +527,7 @@ def test_anchor_gradients_match_oracle(api, rng_mode, n, m, d, r, eps):
 @pytest.mark.parametrize("rng_mode", RANGES)
 @pytest.mark.parametrize("n,m,d,r,eps", [
     (300, 250, 36, 132, 1.0),      # partial anchor block and coordinate tile
-    (4100, 3100, 12, 64, 1.0),     # three row slices, ragged rows
+    (4100, 3100, 12, 64, 1.0),     # twelve row slices, ragged rows
     (260, 140, 128, 256, 0.5),     # 8 coordinate tiles, two anchor blocks
     (150, 170, 200, 68, 2.0),      # 13 tiles: 2 column blocks of 7
 ])
