@@ -540,10 +540,9 @@ int sinkhorn_divergence_accelerated(const sk_problem* p, const sk_solve_opts* op
   int32_t* meta = at<int32_t>(state, L.meta);
   hipLaunchKernelGGL(set_meta_kernel, dim3(1), dim3(64), 0, s, meta, 0);
   SK_HIP(hipGetLastError());
-  SK_HIP(launch_features(p->X, p->n, (int)p->d, p->U, (int)p->r, p->eps, p->q, 0,
-                         at<float>(state, L.phix), at<float>(state, L.sx), s));
-  SK_HIP(launch_features(p->Y, p->m, (int)p->d, p->U, (int)p->r, p->eps, p->q, 0,
-                         at<float>(state, L.phiy), at<float>(state, L.sy), s));
+  SK_HIP(launch_features_pair(p->X, p->n, p->Y, p->m, (int)p->d, p->U, (int)p->r, p->eps,
+                              p->q, 0, at<float>(state, L.phix), at<float>(state, L.sx),
+                              at<float>(state, L.phiy), at<float>(state, L.sy), s));
   std::vector<SolveSpec> specs;
   divergence_specs(p, state, &specs);
   // the three solves run one after the other, reusing the workspace
@@ -613,10 +612,9 @@ int sinkhorn_divergence(const sk_problem* p, const sk_solve_opts* opts,
   hipLaunchKernelGGL(set_meta_kernel, dim3(1), dim3(64), 0, s,
                      at<int32_t>(state, L.meta), xr);
   SK_HIP(hipGetLastError());
-  SK_HIP(launch_features(p->X, p->n, (int)p->d, p->U, (int)p->r, p->eps, p->q,
-                         xr, at<float>(state, L.phix), at<float>(state, L.sx), s));
-  SK_HIP(launch_features(p->Y, p->m, (int)p->d, p->U, (int)p->r, p->eps, p->q,
-                         xr, at<float>(state, L.phiy), at<float>(state, L.sy), s));
+  SK_HIP(launch_features_pair(p->X, p->n, p->Y, p->m, (int)p->d, p->U, (int)p->r, p->eps,
+                              p->q, xr, at<float>(state, L.phix), at<float>(state, L.sx),
+                              at<float>(state, L.phiy), at<float>(state, L.sy), s));
   std::vector<SolveSpec> specs;
   divergence_specs(p, state, &specs);
   size_t need = 0;

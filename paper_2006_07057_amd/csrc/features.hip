@@ -250,13 +250,24 @@ constexpr int kMfmaTilePad = 68;  // floats per row of the LDS transpose tile
 // MODE 0: Gaussian features, linear output; 1: Gaussian, log2 output;
 // 2: arc-cosine features, linear output with the constant column r
 // (width r + 1): l_k = c_k + s log(u_k.x) for u_k.x > 0, else -inf.
+// blockIdx.y = 1 takes the second cloud (X2, n2, Phi2, logscale2) with the
+// same anchors: both clouds of a divergence in one launch.
 template <int MODE>
 __global__ void __launch_bounds__(kBlock)
 features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
                      const float* __restrict__ U, int r,
                      float scale, float neg2e, int s_exp, float lk,
-                     float* __restrict__ Phi, float* __restrict__ logscale) {
+                     float* __restrict__ Phi, float* __restrict__ logscale,
+                     const float* __restrict__ X2, int64_t n2,
+                     float* __restrict__ Phi2, float* __restrict__ logscale2) {
   constexpr bool LOG2 = MODE == 1;
+  if (blockIdx.y == 1) {
+    X = X2;
+    n = n2;
+    Phi = Phi2;
+    logscale = logscale2;
+  }
+  if ((int64_t)blockIdx.x * kMfmaRows >= n) return;   // whole workgroup
   const int W = MODE == 2 ? r + 1 : r;   // output columns (row stride)
   const bool w4 = (W & 3) == 0;
   __shared__ __align__(16) float sA[2][kMfmaRows * kMfmaPad];
@@ -433,9 +444,17 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
 
 bool use_mfma(int d) { return d >= 8 && d % 4 == 0; }
 
-hipError_t launch_mfma(const FeatDesc& D, hipStream_t s) {
-  const int64_t blocks = (D.n + kMfmaRows - 1) / kMfmaRows;
+// D2 (optional): a second cloud with the same anchors, d and r, computed
+// in the same launch.
+hipError_t launch_mfma(const FeatDesc& D, hipStream_t s, const FeatDesc* D2 = nullptr) {
+  const int64_t n_max = D2 && D2->n > D.n ? D2->n : D.n;
+  const int64_t blocks = (n_max + kMfmaRows - 1) / kMfmaRows;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks, D2 ? 2u : 1u);
+  const float* X2 = D2 ? D2->X : nullptr;
+  const int64_t n2 = D2 ? D2->n : 0;
+  float* Phi2 = D2 ? D2->Phi : nullptr;
+  float* s2 = D2 ? D2->s : nullptr;
   const double eps = D.eps, q = D.q;
   if (D.r > SK_MAX_R || D.r % 4 != 0) return hipErrorInvalidValue;
   const float c0 = (float)(-0.5 * log((double)D.r) + 0.25 * D.d * log(2.0 * q));
@@ -447,11 +466,11 @@ hipError_t launch_mfma(const FeatDesc& D, hipStream_t s) {
   const hipError_t e0 = hipGetLastError();
   if (e0 != hipSuccess) return e0;
   if (D.log2_out)
-    hipLaunchKernelGGL(features_mfma_kernel<1>, dim3((unsigned)blocks), dim3(kBlock), 0,
-                       s, D.X, D.n, D.d, D.U, D.r, scale, neg2e, 0, 0.f, D.Phi, D.s);
+    hipLaunchKernelGGL(features_mfma_kernel<1>, grid, dim3(kBlock), 0, s, D.X, D.n, D.d,
+                       D.U, D.r, scale, neg2e, 0, 0.f, D.Phi, D.s, X2, n2, Phi2, s2);
   else
-    hipLaunchKernelGGL(features_mfma_kernel<0>, dim3((unsigned)blocks), dim3(kBlock), 0,
-                       s, D.X, D.n, D.d, D.U, D.r, scale, neg2e, 0, 0.f, D.Phi, D.s);
+    hipLaunchKernelGGL(features_mfma_kernel<0>, grid, dim3(kBlock), 0, s, D.X, D.n, D.d,
+                       D.U, D.r, scale, neg2e, 0, 0.f, D.Phi, D.s, X2, n2, Phi2, s2);
   return hipGetLastError();
 }
 
@@ -660,6 +679,29 @@ hipError_t launch_features(const float* X, int64_t n, int d, const float* U,
   return e;
 }
 
+hipError_t launch_features_pair(const float* X, int64_t n, const float* Y, int64_t m,
+                                int d, const float* U, int r, double eps, double q,
+                                int log2_out, float* PhiX, float* sX, float* PhiY,
+                                float* sY, hipStream_t s) {
+  if (!use_mfma(d)) {
+    const hipError_t e = launch_features(X, n, d, U, r, eps, q, log2_out, PhiX, sX, s);
+    if (e != hipSuccess) return e;
+    return launch_features(Y, m, d, U, r, eps, q, log2_out, PhiY, sY, s);
+  }
+  if (!feat_class(r)) return hipErrorInvalidValue;
+  FeatDesc dx{}, dy{};
+  dx.X = X; dx.U = U; dx.Phi = PhiX; dx.s = sX; dx.n = n;
+  dy.X = Y; dy.U = U; dy.Phi = PhiY; dy.s = sY; dy.n = m;
+  for (FeatDesc* f : {&dx, &dy}) {
+    f->d = d; f->r = r; f->eps = (float)eps; f->q = (float)q; f->tile0 = 0;
+    f->log2_out = log2_out;
+  }
+  void* tok = prof_begin(kProfFeatures, s);
+  const hipError_t e = launch_mfma(dx, s, &dy);
+  prof_end(tok, s);
+  return e;
+}
+
 hipError_t launch_features_batched(const FeatDesc* host, int count,
                                    FeatDesc* dev_scratch, hipStream_t s) {
   if (count <= 0) return hipSuccess;
@@ -725,7 +767,8 @@ hipError_t launch_features_arccos(const float* X, int64_t n, int d, const float*
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
       hipLaunchKernelGGL(features_mfma_kernel<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                         X, n, d, U, r, 1.0f, 0.f, s_exp, lk, Phi, logscale);
+                         X, n, d, U, r, 1.0f, 0.f, s_exp, lk, Phi, logscale, nullptr,
+                         (int64_t)0, nullptr, nullptr);
       e = hipGetLastError();
     }
     prof_end(tok, s);

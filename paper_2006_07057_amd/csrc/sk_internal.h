@@ -101,6 +101,12 @@ struct FeatDesc {
   int32_t pad;
   int64_t tile0;         // first row-tile index of this problem
 };
+// Features of both clouds of a divergence (same anchors): one matrix-core
+// launch for d >= 8, else two launches.
+hipError_t launch_features_pair(const float* X, int64_t n, const float* Y, int64_t m,
+                                int d, const float* U, int r, double eps, double q,
+                                int log2_out, float* PhiX, float* sX, float* PhiY,
+                                float* sY, hipStream_t s);
 hipError_t launch_features_batched(const FeatDesc* host, int count,
                                    FeatDesc* dev_scratch, hipStream_t s);
 
