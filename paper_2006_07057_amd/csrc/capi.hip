@@ -73,6 +73,7 @@ std::map<int, int64_t>& tuning_table() {
 int class_rmax(int r) { return solver_class_rmax(r); }
 
 constexpr int64_t kDefaultTarget = 256 * 1024;
+constexpr int64_t kSideBySideBytes = 256ll << 20;   // feature bytes per iteration
 
 int planned_group(int64_t n, int64_t m, int r) {
   const int cls = class_rmax(r);
@@ -165,12 +166,20 @@ int run_solves(const std::vector<SolveSpec>& specs, const sk_solve_opts* o,
     // workgroups cannot join another).  A launch packing more solves gives
     // each a share of the grid proportional to its work per iteration, so
     // the gangs run side by side instead of queueing for the full grid.
+    // Small solves are the exception: when one iteration streams at most
+    // kSideBySideBytes (about the fixed cost of an iteration's barriers and
+    // reductions at the full streaming rate), running them side by side
+    // overlaps those fixed costs, which would otherwise be paid once per
+    // solve.
     // Shares are rounded up: with T = total work / grid, a gang of
     // ceil(w / T) workgroups finishes within T, while rounding down could
     // stretch a large solve to nearly 2T and set the launch's length (the
     // workgroups of early finishers take the small solves' seats in turn).
+    bool small = true;
+    for (int i : order)
+      small = small && 4 * (specs[i].n + specs[i].m) * (int64_t)specs[i].r <= kSideBySideBytes;
     std::vector<int> gshare(specs.size());
-    if (order.size() > 3) {
+    if (order.size() > 3 || (order.size() > 1 && small)) {
       double total = 0.0;
       for (int i : order) total += (double)(specs[i].n + specs[i].m) * specs[i].r;
       for (int i : order) {
