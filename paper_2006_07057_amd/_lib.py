@@ -140,6 +140,12 @@ def lib():
                 f"{LIB_PATH} is missing: build it with "
                 "`python -m paper_2006_07057_amd.build` (there is no CPU "
                 "fallback)")
+        # torch carries its own HIP runtime.  Load it first, so that this
+        # library's dependency on the runtime resolves to the one torch
+        # uses: the streams and device memory passed in come from torch,
+        # and a second runtime loaded before torch does not know them
+        # (launches then fail with a HIP error).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
