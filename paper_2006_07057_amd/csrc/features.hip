@@ -492,7 +492,8 @@ arccos_features_kernel(const float* __restrict__ X, int64_t n, int d,
                        const float* __restrict__ U, int r, int s, float c0,
                        float cu, float lk, float* __restrict__ Phi,
                        float* __restrict__ logscale) {
-  __shared__ __align__(16) float Ut[kFeatLdsFloats];
+  // transposed anchors (dynamic: d * rp floats when they fit, else none)
+  extern __shared__ __align__(16) float Ut[];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int R1 = r + 1;
@@ -790,7 +791,10 @@ hipError_t launch_features_arccos(const float* X, int64_t n, int d, const float*
 #undef SK_ARC
   if (!fn) return hipErrorInvalidValue;
   void* tok = prof_begin(kProfFeatures, s);
-  hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kBlock), 0, s, X, n, d, U, r, s_exp, c0,
+  // the kernel stages U^T in LDS exactly when d * rp <= kFeatLdsFloats
+  const int64_t rp = (R1 + 3) & ~3;
+  const size_t shmem = (int64_t)d * rp <= kFeatLdsFloats ? (size_t)d * rp * sizeof(float) : 0;
+  hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kBlock), shmem, s, X, n, d, U, r, s_exp, c0,
                      cu, lk, Phi, logscale);
   const hipError_t e = hipGetLastError();
   prof_end(tok, s);
