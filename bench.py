@@ -101,22 +101,29 @@ def make_inputs(wl, seed, api, inputs):
         gen = {"gmm3d": inputs.gmm3d, "pixels": inputs.pixels,
                "sphere": inputs.sphere}[wl["kind"]]
         c = gen(seed, n=wl["n"], m=wl["m"], d=wl["d"])
-        R = inputs.max_norm(c.X, c.Y)
-        q = api.gaussian_q(R, wl["eps"], wl["d"])
-        sigma2 = q * wl["eps"] / 4.0
+        Z = inputs.standard_normal_anchors(seed, wl["r"], wl["d"])
+        U, q = api.gaussian_anchors(Z, wl["eps"], R=inputs.max_norm(c.X, c.Y))
     else:
         c = inputs.gauss2d(seed, n=wl["n"], m=wl["m"], d=wl["d"])
-        sigma2 = wl["sigma2"]
-        q = 4.0 * sigma2 / wl["eps"]
-    U = inputs.gaussian_anchors(seed, wl["r"], wl["d"], sigma2)
+        Z = inputs.standard_normal_anchors(seed, wl["r"], wl["d"])
+        U, q = api.gaussian_anchors(Z, wl["eps"], sigma2=wl["sigma2"])
     return c, U, q
 
 
-def cpu_baseline(c, U, wl, q, iters_total, sample_rows):
+def cpu_baseline(c, wl, seed, iters_total, sample_rows):
     """Time the FP64 oracle (as it stands) on the first `sample_rows` points
     of each cloud, and scale linearly in the number of points to one full
-    divergence with the GPU's iteration counts."""
+    divergence with the GPU's iteration counts.  The oracle forms its own q
+    and anchors from the same seeded draws."""
     import oracle
+    from paper_2006_07057_amd import inputs
+    if "sigma2" in wl:
+        sigma2 = wl["sigma2"]
+        q = oracle.q_from_sigma2(sigma2, wl["eps"])
+    else:
+        q = oracle.lambert_q(inputs.max_norm(c.X, c.Y), wl["eps"], wl["d"])
+        sigma2 = oracle.sigma2_from_q(q, wl["eps"])
+    U = inputs.gaussian_anchors(seed, wl["r"], wl["d"], sigma2)
     try:
         from threadpoolctl import threadpool_info
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
@@ -734,7 +741,7 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on a host sample", file=sys.stderr,
               flush=True)
-        rec["cpu_baseline"] = cpu_baseline(c, U, wl, q, sum(iters),
+        rec["cpu_baseline"] = cpu_baseline(c, wl, args.seed, sum(iters),
                                            args.cpu_sample_rows)
     print(json.dumps(rec), flush=True)
     return 0

@@ -100,7 +100,8 @@ typedef struct {
 
 /* Outcome of one run of Algorithm 1, written by the device.
  *   iters     iterations whose (u, v) are returned;
- *   status    SK_OK, SK_ENOTCONV, SK_ERANGE or SK_ETIMEOUT;
+ *   status    SK_OK, SK_ENOTCONV, SK_ERANGE, SK_ETIMEOUT, or SK_EINVAL for
+ *             weights outside the simplex (see sinkhorn_solve);
  *   err       ||v o K^T u - b||_1 of the returned pair (float64);
  *   w_hat     dual estimate eps (a^T log u + b^T log v) of Eq.
  *             (dual-estimate) for the kernel the solver was given,
@@ -119,6 +120,21 @@ typedef struct {
  * N(0, sigma^2 I_d) with sigma^2 = q eps / 4.  Host-only; writes *q_host.
  * SK_EINVAL if R <= 0, eps <= 0, d <= 0 or q_host is NULL. */
 int sinkhorn_gaussian_q(double R, double eps, int64_t d, double* q_host);
+
+/* Anchors of the Gaussian feature map (Lemma 1): u_k ~ N(0, sigma^2 I_d)
+ * i.i.d. with sigma^2 = q eps / 4, written as U = sigma Z from standard
+ * normal draws Z supplied by the caller (its own seeded generator), so the
+ * randomness stays an input.  Host-only.
+ *   Z_host   r x d float64 standard normal draws (row-major, read only);
+ *   sigma2   if > 0: the anchor variance itself, and q = 4 sigma2 / eps;
+ *            otherwise q is Lemma 1's Lambert bandwidth for points in the
+ *            ball of radius R (as sinkhorn_gaussian_q) and sigma2 = q eps / 4;
+ *   U_host   r x d float32 output, U = (float)(sqrt(sigma2) Z);
+ *   q_host   receives q (pass it to sinkhorn_features / sk_problem.q).
+ * SK_EINVAL for null pointers, r < 1, d < 1, eps <= 0, a non-finite
+ * sigma2, or (sigma2 <= 0) an invalid R. */
+int sinkhorn_gaussian_anchors(const double* Z_host, int64_t r, int64_t d, double eps,
+                              double sigma2, double R, float* U_host, double* q_host);
 
 /* ------------------------------------------------------------------ (a2) */
 /* Positive Gaussian features, row-scaled.  For each point x_i (row of X)
@@ -174,6 +190,12 @@ size_t sinkhorn_solve_workspace_size(int64_t n, int64_t m, int64_t r);
  *          u is read as the starting point when opts->warm_start != 0.
  * ws:      device workspace of at least sinkhorn_solve_workspace_size bytes,
  *          used as scratch (contents on entry are ignored).
+ * Weights: a and b must be probability vectors with positive entries (a in
+ *          the simplex, Sec. 2).  The solver checks them on the device in
+ *          float64 before iterating; an entry that is not positive and
+ *          finite, or a sum farther than 1e-5 from 1, ends the solve at
+ *          once with info->status = SK_EINVAL (iters 0, w_hat NaN).  The
+ *          same holds for every entry point that runs Algorithm 1.
  * Errors:  SK_EINVAL (sizes, pointers, tol < 0, max_iter < 1),
  *          SK_ENOMEM (ws too small), SK_ENOTSUP (r % 4 != 0 or r > 4096). */
 int sinkhorn_solve(const float* Phix, int64_t n, const float* Phiy, int64_t m,
@@ -232,6 +254,38 @@ size_t sinkhorn_divergence_workspace_size(const sk_problem* p);
 int sinkhorn_divergence(const sk_problem* p, const sk_solve_opts* opts,
                         double* out, void* state, size_t state_bytes,
                         void* ws, size_t ws_bytes, sk_stream_t stream);
+
+/* Debiased divergence on the perturbed arc-cosine features of
+ * sinkhorn_features_arccos: the
+ * cost is -eps log k_{s,kappa}, K = Phi_x Phi_y^T with r + 1 columns, and
+ * W_bar = W(mu,nu) - (W(mu,mu) + W(nu,nu)) / 2 (Eq. reg-sdiv) with each term
+ * the dual estimate of one run of Algorithm 1 in the linear domain.
+ *   p      problem; p->q is not used, p->r anchors (r + 1 feature columns:
+ *          (r + 1) % 4 == 0 and r + 1 <= SK_MAX_R);
+ *   opts   opts->range must be SK_RANGE_LINEAR;
+ *   out    device double[4] = {W_bar, W_xy, W_xx, W_yy};
+ *   state  device buffer of sinkhorn_state_layout(n, m, r + 1).total bytes
+ *          (features with r + 1 columns, scalings, infos);
+ *   ws     sinkhorn_divergence_arccos_workspace_size(p) bytes.
+ * The gradient entry points (which differentiate the Gaussian map) do not
+ * apply to this state.  Errors: SK_EINVAL (pointers, sizes, eps, s outside
+ * 0..8, sigma <= 1, kappa <= 0, opts), SK_ENOTSUP (column count, range),
+ * SK_ENOMEM (state or workspace too small). */
+size_t sinkhorn_divergence_arccos_workspace_size(const sk_problem* p);
+int sinkhorn_divergence_arccos(const sk_problem* p, int32_t s, double sigma,
+                               double kappa, const sk_solve_opts* opts, double* out,
+                               void* state, size_t state_bytes, void* ws, size_t ws_bytes,
+                               sk_stream_t stream);
+
+/* W_bar = W_xy - (W_xx + W_yy) / 2 (Eq. reg-sdiv) in float64 from the dual
+ * estimates of device-resident solve records, for divergences whose three
+ * solves were run by sinkhorn_solve_batched (e.g. a serving loop).
+ *   infos  device array of 3 * count records, (xy, xx, yy) per problem;
+ *   out    device double[4 * count]: {W_bar, W_xy, W_xx, W_yy} per problem.
+ * A failed solve's NaN estimate propagates into W_bar.  Stream-ordered.
+ * Errors: SK_EINVAL (null pointer, count < 1), SK_EHIP. */
+int sinkhorn_divergence_assemble(const sk_solve_info* infos, int32_t count, double* out,
+                                 sk_stream_t stream);
 
 /* ------------------------------------------------------------------ (a6) */
 /* Workspace bytes for a batch of `count` problems (host). */

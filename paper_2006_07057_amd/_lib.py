@@ -56,6 +56,8 @@ class sk_state_layout(ctypes.Structure):
 SIGNATURES = {
     "sinkhorn_gaussian_q": (c_i32, [c_dbl, c_dbl, c_i64,
                                     ctypes.POINTER(ctypes.c_double)]),
+    "sinkhorn_gaussian_anchors": (c_i32, [c_void, c_i64, c_i64, c_dbl, c_dbl, c_dbl,
+                                          c_void, ctypes.POINTER(ctypes.c_double)]),
     "sinkhorn_features": (c_i32, [c_void, c_i64, c_i64, c_void, c_i64, c_dbl,
                                   c_dbl, c_i32, c_void, c_void, c_void]),
     "sinkhorn_features_arccos": (c_i32, [c_void, c_i64, c_i64, c_void, c_i64, c_i32,
@@ -71,6 +73,11 @@ SIGNATURES = {
     "sinkhorn_divergence": (c_i32, [ctypes.POINTER(sk_problem),
                                     ctypes.POINTER(sk_solve_opts), c_void,
                                     c_void, c_size, c_void, c_size, c_void]),
+    "sinkhorn_divergence_arccos_workspace_size": (c_size, [ctypes.POINTER(sk_problem)]),
+    "sinkhorn_divergence_arccos": (c_i32, [ctypes.POINTER(sk_problem), c_i32, c_dbl, c_dbl,
+                                           ctypes.POINTER(sk_solve_opts), c_void, c_void,
+                                           c_size, c_void, c_size, c_void]),
+    "sinkhorn_divergence_assemble": (c_i32, [c_void, c_i32, c_void, c_void]),
     "sinkhorn_batched_workspace_size": (c_size, [ctypes.POINTER(sk_problem),
                                                  c_i32]),
     "sinkhorn_divergence_batched": (c_i32, [ctypes.POINTER(sk_problem), c_i32,

@@ -90,6 +90,28 @@ def gaussian_q(R: float, eps: float, d: int) -> float:
     return q.value
 
 
+def gaussian_anchors(Z: np.ndarray, eps: float, sigma2: Optional[float] = None,
+                     R: Optional[float] = None):
+    """Anchors of Lemma 1 from standard normal draws Z (r x d, the caller's
+    seeded randomness): U = sqrt(sigma2) Z with sigma2 given, or with
+    sigma2 = q eps / 4 and q Lemma 1's bandwidth for points of norm <= R.
+    Host call into the library; returns (U float32 (r, d), q)."""
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    if Z.ndim != 2:
+        raise ValueError("Z must be r x d")
+    r, d = Z.shape
+    if (sigma2 is None) == (R is None):
+        raise ValueError("give exactly one of sigma2 and R")
+    U = np.empty((r, d), dtype=np.float32)
+    q = ctypes.c_double()
+    check(lib().sinkhorn_gaussian_anchors(Z.ctypes.data, r, d, float(eps),
+                                          float(sigma2) if sigma2 is not None else 0.0,
+                                          float(R) if R is not None else 0.0,
+                                          U.ctypes.data, ctypes.byref(q)),
+          "sinkhorn_gaussian_anchors")
+    return U, q.value
+
+
 # ------------------------------------------------------------------ (a2)
 def features(X: torch.Tensor, U: torch.Tensor, eps: float, q: float,
              range: int = EXTENDED):
@@ -131,29 +153,48 @@ def features_arccos(X: torch.Tensor, U: torch.Tensor, s: int, sigma: float,
 
 def divergence_arccos(X, Y, a, b, U, s: int, sigma: float, kappa: float, eps: float,
                       tol=1e-6, max_iter=2000, fixed_iter=0):
-    """Debiased divergence for the arc-cosine kernel (cost -eps log k_{s,kappa}):
-    features of both clouds, then the three solves in one packed launch
-    (linear domain).  Returns (W_bar, infos) (synchronises)."""
-    Px, sx = features_arccos(X, U, s, sigma, kappa)
-    Py, sy = features_arccos(Y, U, s, sigma, kappa)
-    n, m, r1 = Px.shape[0], Py.shape[0], Px.shape[1]
+    """Debiased divergence for the arc-cosine kernel (cost -eps log k_{s,kappa})
+    through sinkhorn_divergence_arccos: features of both clouds, the three
+    solves in one packed launch (linear domain), W_bar on the device.
+    Returns (W_bar, infos) (synchronises)."""
+    _check_problem_tensors(X, Y, a, b, U)
+    n, d = X.shape
+    m, r = Y.shape[0], U.shape[0]
     dev = X.device
-    buf = lambda k: torch.empty(2 * k, dtype=torch.float32, device=dev)
-    infos = torch.zeros(3 * INFO_BYTES, dtype=torch.uint8, device=dev)
-    keep = []
-    specs = []
-    for t, (P, Q, p, g, sp, sq, rows, cols) in enumerate(
-            ((Px, Py, a, b, sx, sy, n, m), (Px, Px, a, a, sx, sx, n, n),
-             (Py, Py, b, b, sy, sy, m, m))):
-        u, v, w, z = buf(rows), buf(cols), buf(r1), buf(r1)
-        keep.append((u, v, w, z))
-        info = infos[t * INFO_BYTES:(t + 1) * INFO_BYTES]
-        specs.append(solve_spec(P, Q, p, g, u, v, w, z, info, eps=eps, srow=sp, scol=sq))
-    solve_batched(specs, tol=tol, max_iter=max_iter, fixed_iter=fixed_iter,
-                  range=LINEAR, device=dev)
-    rec = parse_infos(infos)
-    wh = rec["w_hat"]
-    return float(wh[0] - 0.5 * (wh[1] + wh[2])), rec
+    prob = sk_problem(X.data_ptr(), Y.data_ptr(), a.data_ptr(), b.data_ptr(),
+                      U.data_ptr(), n, m, d, r, float(eps), 0.0)
+    L = state_layout(n, m, r + 1)
+    state = torch.empty(L.total, dtype=torch.uint8, device=dev)
+    need = int(lib().sinkhorn_divergence_arccos_workspace_size(ctypes.byref(prob)))
+    if need == 0:
+        raise _lib.SinkhornError(_lib.SK_ENOTSUP, "sinkhorn_divergence_arccos_workspace_size")
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    out = torch.empty(4, dtype=torch.float64, device=dev)
+    o = _opts(tol, max_iter, fixed_iter, False, LINEAR)
+    check(lib().sinkhorn_divergence_arccos(ctypes.byref(prob), int(s), float(sigma),
+                                           float(kappa), ctypes.byref(o), _ptr(out),
+                                           _ptr(state), state.numel(), _ptr(ws), ws.numel(),
+                                           _stream(dev)), "sinkhorn_divergence_arccos")
+    rec = parse_infos(state[L.info:L.info + 3 * INFO_BYTES])
+    return float(out[0].item()), rec
+
+
+def divergence_assemble(infos: torch.Tensor, count: int,
+                        out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """W_bar and the three dual estimates of `count` divergences from their
+    device solve records (3 consecutive sk_solve_info per problem, as bytes)
+    via sinkhorn_divergence_assemble.  Returns a device float64 tensor
+    (count, 4) = (W_bar, W_xy, W_xx, W_yy) (asynchronous)."""
+    if infos.dtype != torch.uint8 or not infos.is_cuda or not infos.is_contiguous():
+        raise ValueError("infos must be a contiguous device uint8 tensor")
+    if infos.numel() < 3 * count * INFO_BYTES:
+        raise ValueError("infos holds fewer than 3 * count records")
+    if out is None:
+        out = torch.empty((count, 4), dtype=torch.float64, device=infos.device)
+    check(lib().sinkhorn_divergence_assemble(_ptr(infos), int(count), _ptr(out),
+                                             _stream(infos.device)),
+          "sinkhorn_divergence_assemble")
+    return out
 
 
 # -------------------------------------------------------------- (a3)(a4)

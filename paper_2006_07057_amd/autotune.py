@@ -41,9 +41,10 @@ def class_of(r: int) -> int:
 
 def _problem(n: int, m: int, r: int, d: int, eps: float, seed: int, rng: int, dev):
     c = inputs.gauss2d(seed, n=n, m=m, d=d)
-    # Lemma 1's bandwidth for these points (valid for every eps and d)
-    q = api.gaussian_q(inputs.max_norm(c.X, c.Y), eps, d)
-    U = inputs.gaussian_anchors(seed, r, d, q * eps / 4.0)
+    # anchors with Lemma 1's bandwidth for these points (valid for every
+    # eps and d)
+    U, q = api.gaussian_anchors(inputs.standard_normal_anchors(seed, r, d), eps,
+                                R=inputs.max_norm(c.X, c.Y))
     t = lambda x: torch.from_numpy(x).to(dev)
     Px, _ = api.features(t(c.X), t(U), eps, q, range=rng)
     Py, _ = api.features(t(c.Y), t(U), eps, q, range=rng)

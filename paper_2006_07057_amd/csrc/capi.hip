@@ -135,7 +135,7 @@ int run_solves(const std::vector<SolveSpec>& specs, const sk_solve_opts* o,
     cb.bars = cv.take<unsigned>(kv.second.size());
     cb.descs = cv.take<SolveDesc>(kv.second.size());
     cb.members = cv.take<int32_t>((size_t)sg);
-    cb.dpart = cv.take<double>((size_t)sg * 4);
+    cb.dpart = cv.take<double>((size_t)sg * kDpartSlots);
     bufs[kv.first] = cb;
     for (int i : kv.second) {
       v2[i] = cv.take<float>(2 * (size_t)specs[i].m);
@@ -204,7 +204,7 @@ int run_solves(const std::vector<SolveSpec>& specs, const sk_solve_opts* o,
       D.slots = slots;
       D.slot_stride = 2 * rmax;
       D.members = cb.members + moff;
-      D.dpart = cb.dpart + 4 * moff;
+      D.dpart = cb.dpart + kDpartSlots * moff;
       D.bar = cb.bars + k;
       D.info = sp.info;
       D.tol = o->tol;
@@ -256,6 +256,19 @@ __global__ void assemble_kernel(const AsmDesc* descs, AsmDesc one, int count) {
   }
 }
 
+// The same for `count` problems whose three records are consecutive in
+// `infos` (xy, xx, yy per problem): out[4i..4i+3] = {W_bar, W_xy, W_xx, W_yy}.
+__global__ void assemble_strided_kernel(const sk_solve_info* infos, double* out, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const double wxy = infos[3 * i].w_hat, wxx = infos[3 * i + 1].w_hat,
+               wyy = infos[3 * i + 2].w_hat;
+  out[4 * i] = wxy - 0.5 * (wxx + wyy);
+  out[4 * i + 1] = wxy;
+  out[4 * i + 2] = wxx;
+  out[4 * i + 3] = wyy;
+}
+
 // Records the numeric domain in a state before its features are computed,
 // so a backward pass always sees a defined flag.
 __global__ void set_meta_kernel(int32_t* meta, int32_t xr) {
@@ -273,6 +286,21 @@ int check_problem(const sk_problem* p) {
   if (!(p->eps > 0.0) || !isfinite(p->eps)) return SK_EINVAL;
   if (!(p->q > 0.5) || !isfinite(p->q)) return SK_EINVAL;
   if (p->r > SK_MAX_R || p->r % 4 != 0) return SK_ENOTSUP;
+  if (p->n > (int64_t)1 << 40 || p->m > (int64_t)1 << 40 || p->d > (1 << 20))
+    return SK_EINVAL;
+  return SK_OK;
+}
+
+// A divergence problem on arc-cosine features: q is not used; the solves
+// see r + 1 columns, which the solver needs to be a multiple of 4.
+int check_arccos_problem(const sk_problem* p) {
+  if (!p) return SK_EINVAL;
+  if (bad_ptr(p->X) || bad_ptr(p->Y) || bad_ptr(p->a) || bad_ptr(p->b) ||
+      bad_ptr(p->U))
+    return SK_EINVAL;
+  if (p->n < 1 || p->m < 1 || p->d < 1 || p->r < 1) return SK_EINVAL;
+  if (!(p->eps > 0.0) || !isfinite(p->eps)) return SK_EINVAL;
+  if (p->r + 1 > SK_MAX_R || (p->r + 1) % 4 != 0) return SK_ENOTSUP;
   if (p->n > (int64_t)1 << 40 || p->m > (int64_t)1 << 40 || p->d > (1 << 20))
     return SK_EINVAL;
   return SK_OK;
@@ -564,6 +592,86 @@ int sinkhorn_divergence_accelerated(const sk_problem* p, const sk_solve_opts* op
   }
   AsmDesc one{at<sk_solve_info>(state, L.info), at<double>(state, L.out), out, nullptr,
               0, 0};
+  hipLaunchKernelGGL(assemble_kernel, dim3(1), dim3(64), 0, s, nullptr, one, 1);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+int sinkhorn_divergence_assemble(const sk_solve_info* infos, int32_t count, double* out,
+                                 sk_stream_t stream) {
+  if (!infos || !out || count < 1) return SK_EINVAL;
+  hipLaunchKernelGGL(assemble_strided_kernel, dim3((count + 63) / 64), dim3(64), 0,
+                     S(stream), infos, out, count);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+int sinkhorn_gaussian_anchors(const double* Z_host, int64_t r, int64_t d, double eps,
+                              double sigma2, double R, float* U_host, double* q_host) {
+  if (!Z_host || !U_host || !q_host || r < 1 || d < 1) return SK_EINVAL;
+  if (!(eps > 0.0) || !isfinite(eps)) return SK_EINVAL;
+  double q;
+  if (sigma2 > 0.0) {
+    if (!isfinite(sigma2)) return SK_EINVAL;
+    q = 4.0 * sigma2 / eps;              // sigma^2 = q eps / 4 (Lemma 1)
+  } else {
+    const int rc = sinkhorn_gaussian_q(R, eps, d, &q);
+    if (rc != SK_OK) return rc;
+    sigma2 = q * eps / 4.0;
+  }
+  const double sigma = sqrt(sigma2);
+  for (int64_t i = 0; i < r * d; ++i) U_host[i] = (float)(sigma * Z_host[i]);
+  *q_host = q;
+  return SK_OK;
+}
+
+size_t sinkhorn_divergence_arccos_workspace_size(const sk_problem* p) {
+  if (check_arccos_problem(p) != SK_OK) return 0;
+  sk_problem q = *p;
+  q.r = p->r + 1;
+  std::vector<SolveSpec> specs;
+  divergence_specs(&q, nullptr, &specs);
+  size_t need = 0;
+  sk_solve_opts o{};
+  o.max_iter = 1;
+  o.range = SK_RANGE_LINEAR;
+  run_solves(specs, &o, nullptr, 0, &need, nullptr);
+  return need;
+}
+
+int sinkhorn_divergence_arccos(const sk_problem* p, int32_t s_exp, double sigma,
+                               double kappa, const sk_solve_opts* opts, double* out,
+                               void* state, size_t state_bytes, void* ws, size_t ws_bytes,
+                               sk_stream_t stream) {
+  int rc = check_arccos_problem(p);
+  if (rc) return rc;
+  rc = check_opts(opts);
+  if (rc) return rc;
+  if (opts->range != SK_RANGE_LINEAR) return SK_ENOTSUP;
+  if (s_exp < 0 || s_exp > 8) return SK_EINVAL;
+  if (!(sigma > 1.0) || !(kappa > 0.0) || !isfinite(sigma) || !isfinite(kappa))
+    return SK_EINVAL;
+  if (!state || !ws) return SK_EINVAL;
+  sk_problem q = *p;          // the solves see r + 1 feature columns
+  q.r = p->r + 1;
+  sk_state_layout L;
+  layout_of(q.n, q.m, q.r, &L);
+  if (state_bytes < L.total) return SK_ENOMEM;
+  if (ws_bytes < sinkhorn_divergence_arccos_workspace_size(p)) return SK_ENOMEM;
+  hipStream_t s = S(stream);
+  int32_t* meta = at<int32_t>(state, L.meta);
+  hipLaunchKernelGGL(set_meta_kernel, dim3(1), dim3(64), 0, s, meta, 0);
+  SK_HIP(hipGetLastError());
+  SK_HIP(launch_features_arccos(p->X, p->n, (int)p->d, p->U, (int)p->r, s_exp, sigma, kappa,
+                                at<float>(state, L.phix), at<float>(state, L.sx), s));
+  SK_HIP(launch_features_arccos(p->Y, p->m, (int)p->d, p->U, (int)p->r, s_exp, sigma, kappa,
+                                at<float>(state, L.phiy), at<float>(state, L.sy), s));
+  std::vector<SolveSpec> specs;
+  divergence_specs(&q, state, &specs);
+  size_t need = 0;
+  rc = run_solves(specs, opts, ws, ws_bytes, &need, s);
+  if (rc) return rc;
+  AsmDesc one{at<sk_solve_info>(state, L.info), at<double>(state, L.out), out, meta, 0, 0};
   hipLaunchKernelGGL(assemble_kernel, dim3(1), dim3(64), 0, s, nullptr, one, 1);
   SK_HIP(hipGetLastError());
   return SK_OK;

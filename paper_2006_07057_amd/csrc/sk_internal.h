@@ -30,7 +30,8 @@ struct SolveDesc {
   float* z;              // r: result Prow^T u
   float* slots;          // per-workgroup partial r-vectors, stride slot_stride
   int32_t* members;      // g entries: workgroup index holding each seat
-  double* dpart;         // 4 x g float64 partials (error, flags, dual sums)
+  double* dpart;         // kDpartSlots x g float64 partials (error, flags,
+                         // dual sums, weight sums and weight flags)
   unsigned* bar;         // group barrier counter (zeroed before the launch)
   sk_solve_info* info;   // result record
   double tol;
@@ -45,6 +46,9 @@ struct SolveDesc {
   int32_t slot_stride;   // floats between consecutive workgroup slots
   int32_t pad0;
 };
+
+// float64 partials per workgroup seat of a solve (SolveDesc::dpart).
+constexpr int kDpartSlots = 6;
 
 // Launch-wide control block (zeroed by init_ctl before each launch).
 struct LaunchCtl {

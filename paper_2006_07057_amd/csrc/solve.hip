@@ -50,6 +50,9 @@ constexpr int MODE_UPDATE_CHECK = 2;  // as UPDATE + error of previous s
 constexpr int MODE_CHECK = 3;         // error of previous s only
 
 constexpr float kNegBig = -1.0e30f;   // "log of zero" sentinel (finite)
+// Weights must be probability vectors with positive entries (Sec. 2: a in
+// the simplex); their sum is checked in float64 to this tolerance.
+constexpr double kWeightSumTol = 1e-5;
 
 __device__ __forceinline__ float4 f4zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
 __device__ __forceinline__ float4 f4fill(float v) { return make_float4(v, v, v, v); }
@@ -1050,6 +1053,34 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
   bool ok = true;
   if (threadIdx.x == 0) cst(D.members + br, (int32_t)blockIdx.x);
 
+  // Weight check: every workgroup sums its own rows of a and columns of b
+  // in float64 and counts entries that are not positive and finite; the
+  // partials are published with the first half-step's (whose barrier makes
+  // them visible) and every workgroup takes the same decision after it.
+  double wsum_a = 0.0, wsum_b = 0.0, wbad = 0.0;
+  {
+    const float* wa = uniform_ptr(D.a);
+    const float* wb = uniform_ptr(D.b);
+    for (int64_t i = rlo() + threadIdx.x; i < rhi(); i += kBlock) {
+      const float x = wa[i];
+      wsum_a += (double)x;
+      if (!(x > 0.f) || !isfinite(x)) wbad += 1.0;
+    }
+    for (int64_t j = clo() + threadIdx.x; j < chi(); j += kBlock) {
+      const float x = wb[j];
+      wsum_b += (double)x;
+      if (!(x > 0.f) || !isfinite(x)) wbad += 1.0;
+    }
+    wsum_a = block_dsum(wsum_a, sh.d);
+    wsum_b = block_dsum(wsum_b, sh.d);
+    wbad = block_dsum(wbad, sh.d);
+    if (threadIdx.x == 0) {
+      cst(D.dpart + 3 * g + br, wsum_a);
+      cst(D.dpart + 4 * g + br, wsum_b);
+      cst(D.dpart + 5 * g + br, wbad);
+    }
+  }
+
   // z^(0) = Prow^T u^(0), u^(0) = 1 or the caller's start.
   Dom::template zero<false>(S);
   Dom::template half_step<MODE_ACCUM>(uniform_ptr(D.Prow), rlo(), rhi(), r,
@@ -1066,6 +1097,16 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
   const bool fixed = D.fixed_iter > 0;
   const int limit = uniform_i32(fixed ? D.fixed_iter : D.max_iter);
   if (ok && bad) status = SK_ERANGE;
+  if (ok) {
+    if (g > 1) {
+      wsum_a = group_dsum(D.dpart + 3 * g, g, sh.d);
+      wsum_b = group_dsum(D.dpart + 4 * g, g, sh.d);
+      wbad = group_dsum(D.dpart + 5 * g, g, sh.d);
+    }
+    if (wbad > 0.0 || !(fabs(wsum_a - 1.0) <= kWeightSumTol) ||
+        !(fabs(wsum_b - 1.0) <= kWeightSumTol))
+      status = SK_EINVAL;
+  }
 
   for (int k = 1; ok && status == SK_OK; ++k) {
     const bool last = k > limit;

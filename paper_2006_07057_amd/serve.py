@@ -74,18 +74,17 @@ class Result:
 
 def from_spec(spec, sigma2: Optional[float] = None) -> Request:
     """Materialise a synthetic request description (``inputs.Request``):
-    points and weights from its seed, q from the Lambert rule of Lemma 1
-    (R = largest norm over both clouds) unless sigma2 is given, anchors
-    drawn from N(0, sigma2 I) with sigma2 = q eps / 4."""
+    points and weights from its seed, and anchors of Lemma 1 from the
+    request's standard normal draws through sinkhorn_gaussian_anchors (q
+    from the Lambert rule with R = largest norm over both clouds, unless
+    sigma2 is given)."""
     from . import inputs
     cloud = inputs.request_arrays(spec)
+    Z = inputs.standard_normal_anchors(spec.seed, spec.r, spec.d)
     if sigma2 is None:
-        R = inputs.max_norm(cloud.X, cloud.Y)
-        q = api.gaussian_q(R, spec.eps, spec.d)
-        sigma2 = q * spec.eps / 4.0
+        U, q = api.gaussian_anchors(Z, spec.eps, R=inputs.max_norm(cloud.X, cloud.Y))
     else:
-        q = 4.0 * sigma2 / spec.eps
-    U = inputs.gaussian_anchors(spec.seed, spec.r, spec.d, sigma2)
+        U, q = api.gaussian_anchors(Z, spec.eps, sigma2=sigma2)
     return Request(cloud.X, cloud.Y, cloud.a, cloud.b, U, spec.eps, q,
                    arrival=spec.arrival, rid=spec.rid)
 
@@ -133,7 +132,6 @@ class _Live:
         self.bytes = footprint_bytes(n, m, d, r)
         self.done = [False, False, False]
         self.iters = [0, 0, 0]
-        self.w_hat = [math.nan] * 3
         self.status = SK_OK
         self.admitted = now
         self.epochs = 0
@@ -156,6 +154,19 @@ class _Live:
 
     def _f32(self, off, count):
         return self.buf[off:off + 4 * count].view(torch.float32)
+
+    def keep_record(self, k: int, rec: torch.Tensor):
+        """Store solve k's final device record in the state (device copy)."""
+        o = self.layout.info + k * api.INFO_BYTES
+        self.buf[o:o + api.INFO_BYTES].copy_(rec)
+
+    def assemble(self):
+        """W_bar and the three estimates into the state's out block, on the
+        device (sinkhorn_divergence_assemble); returns that float64 view."""
+        L = self.layout
+        out = self.buf[L.out:L.out + 32].view(torch.float64).view(1, 4)
+        api.divergence_assemble(self.buf[L.info:L.info + 3 * api.INFO_BYTES], 1, out)
+        return out
 
     def spec(self, k: int, info_ptr: int):
         L, n, m, r = self.layout, self.n, self.m, self.r
@@ -260,29 +271,31 @@ class Server:
             lv.iters[k] += it
             if st == SK_OK:
                 lv.done[k] = True
-                lv.w_hat[k] = float(rec["w_hat"][j])
             elif st == SK_ENOTCONV:
                 if lv.iters[k] >= self.max_iter:
                     lv.done[k] = True
                     lv.status = SK_ENOTCONV
-                    lv.w_hat[k] = float(rec["w_hat"][j])
             else:
                 lv.done[k] = True
                 lv.status = st
+            if lv.done[k]:
+                lv.keep_record(k, infos[j * api.INFO_BYTES:(j + 1) * api.INFO_BYTES])
         for lv in self.live:
             lv.epochs += 1
-        finished = []
         t = self.now()
-        keep = []
+        keep, done = [], []
         for lv in self.live:
-            if all(lv.done):
-                wxy, wxx, wyy = lv.w_hat
-                res = Result(lv.req.rid, lv.status, wxy - 0.5 * (wxx + wyy), tuple(lv.w_hat),
-                             tuple(lv.iters), lv.req.arrival, lv.admitted, t, lv.epochs)
-                finished.append(res)
+            (done if all(lv.done) else keep).append(lv)
+        finished = []
+        if done:
+            # W_bar of every finished request assembled on the device, read
+            # back in one transfer
+            vals = torch.cat([lv.assemble() for lv in done]).cpu().numpy()
+            for lv, v in zip(done, vals):
+                finished.append(Result(lv.req.rid, lv.status, float(v[0]),
+                                       tuple(float(x) for x in v[1:]), tuple(lv.iters),
+                                       lv.req.arrival, lv.admitted, t, lv.epochs))
                 self.live_bytes -= lv.bytes
-            else:
-                keep.append(lv)
         self.live = keep
         self.results.extend(finished)
         self.epoch_log.append({"t": t, "solves": len(jobs), "admitted": admitted,

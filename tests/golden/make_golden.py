@@ -7,7 +7,8 @@ method's arithmetic); nothing is taken from the GPU library.  The paper
 prints no worked example with numbers for this path, so the fixtures are
 oracle values, each stamped with the recipe that reproduces it:
 
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py             # the quick fixtures
+    python tests/golden/make_golden.py gmm3d_1m    # the 10^6-point mixture
 """
 import json
 import os
@@ -24,7 +25,7 @@ from paper_2006_07057_amd import inputs  # noqa: E402
 
 
 def gauss2d_1k():
-    """Two 2-D Gaussians (the setting of Sec. 5's first experiment):
+    """Two 2-D Gaussians (the setting of the first experiment of Sec. 4):
     x ~ N(0, I), y ~ N(1.5 1, I), n = m = 1000, uniform weights, eps = 0.5,
     r = 128 anchors from N(0, I) (sigma^2 = 1, q = 4 sigma^2 / eps), 200
     fixed iterations of Algorithm 1 from u = 1 on the dense K_theta."""
@@ -83,15 +84,76 @@ def accelerated_small():
             "min_block_margin": min(res.margins), "min_test_margin": min(res.ls_margins)}
 
 
-def main():
-    for name, fn in (("gauss2d_1k", gauss2d_1k), ("lambert_q", lambert_q),
-                     ("accelerated_small", accelerated_small)):
+def _gmm3d_1m_features():
+    """Row-scaled float64 features of the 10^6-point mixture workload, built
+    by oracle.gaussian_features_scaled on blocks of rows (each row's
+    features depend on that row alone, so this is the same array as one
+    call on all rows, in a quarter of the memory)."""
+    c = inputs.gmm3d(0)
+    eps, r = 0.1, 1024
+    q = oracle.lambert_q(inputs.max_norm(c.X, c.Y), eps, 3)
+    U = inputs.gaussian_anchors(0, r, 3, oracle.sigma2_from_q(q, eps))
+    feats = []
+    for Z in (c.X, c.Y):
+        P = np.empty((Z.shape[0], r))
+        s = np.empty(Z.shape[0])
+        for i in range(0, Z.shape[0], 1 << 16):
+            P[i:i + (1 << 16)], s[i:i + (1 << 16)] = oracle.gaussian_features_scaled(
+                Z[i:i + (1 << 16)], U, eps, q)
+        feats.append((P, s))
+    return c, U, eps, q, (feats[0][0], feats[0][1], feats[1][0], feats[1][1])
+
+
+GMM3D_RECIPE = ("inputs.gmm3d(0) (n = m = 10^6, d = 3); eps = 0.1; r = 1024; "
+                "q = oracle.lambert_q(inputs.max_norm(X, Y), 0.1, 3); "
+                "U = inputs.gaussian_anchors(0, 1024, 3, oracle.sigma2_from_q(q, 0.1)); "
+                "oracle.divergence_scaled(..., dense=False) on the row-scaled features")
+
+
+def _div_record(div):
+    return {"W_bar": div.value, "W_xy": div.w_xy, "W_xx": div.w_xx, "W_yy": div.w_yy,
+            "iters": [div.xy.iters, div.xx.iters, div.yy.iters],
+            "err": [div.xy.err, div.xx.err, div.yy.err]}
+
+
+def gmm3d_1m():
+    """The 10^6-point mixture workload (two 4-component Gaussian mixtures in
+    R^3, eps = 0.1, r = 1024) through the factored float64 oracle: 100
+    fixed iterations, and the stop test of Algorithm 1 at tol = 1e-6 with
+    at most 2000 iterations.  About an hour on 8 cores and 20 GB of memory."""
+    import time
+    c, U, eps, q, feats = _gmm3d_1m_features()
+    out = {"recipe": GMM3D_RECIPE, "eps": eps, "q": q, "r": 1024}
+    t0 = time.time()
+    div = oracle.divergence_scaled(c.X, c.Y, c.a, c.b, U, eps, q, fixed_iter=100,
+                                   dense=False, features=feats)
+    out["fixed_100"] = _div_record(div)
+    print(f"gmm3d_1m: 100 fixed iterations in {time.time() - t0:.0f} s", flush=True)
+    t0 = time.time()
+    div = oracle.divergence_scaled(c.X, c.Y, c.a, c.b, U, eps, q, tol=1e-6, max_iter=2000,
+                                   dense=False, features=feats)
+    out["tol_1e-6"] = _div_record(div)
+    print(f"gmm3d_1m: tol 1e-6 in {time.time() - t0:.0f} s", flush=True)
+    return out
+
+
+# fixtures regenerated by default; the 10^6-point one only when named
+FIXTURES = {"gauss2d_1k": gauss2d_1k, "lambert_q": lambert_q,
+            "accelerated_small": accelerated_small}
+LONG_FIXTURES = {"gmm3d_1m": gmm3d_1m}
+
+
+def main(names=None):
+    names = names or list(FIXTURES)
+    for name in names:
+        fn = FIXTURES.get(name) or LONG_FIXTURES[name]
+        rec = fn()
         path = os.path.join(HERE, name + ".json")
         with open(path, "w") as f:
-            json.dump(fn(), f, indent=1)
+            json.dump(rec, f, indent=1)
             f.write("\n")
         print("wrote", path)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:])

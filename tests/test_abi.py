@@ -153,3 +153,74 @@ def test_workspace_sizes_grow_with_the_problem(L):
     assert L.sinkhorn_solve_workspace_size(0, 10, 8) == 0
     # bounded by the slot buffer, not by n: no quadratic growth
     assert big < 64 * 2 ** 20
+
+
+# ------------------------------------------------- anchors, assembly, arccos
+@pytest.mark.parametrize("r,d,eps,sigma2", [(128, 2, 0.5, 1.0), (64, 16, 0.05, 0.3)])
+def test_gaussian_anchors_with_given_variance(L, r, d, eps, sigma2):
+    """sigma^2 given: U = float32(sqrt(sigma^2) Z) exactly as the seeded
+    generator's own anchors, and q = 4 sigma^2 / eps (Lemma 1's relation)."""
+    from paper_2006_07057_amd import inputs
+    Z = inputs.standard_normal_anchors(3, r, d)
+    U = np.empty((r, d), np.float32)
+    q = ctypes.c_double()
+    assert L.sinkhorn_gaussian_anchors(Z.ctypes.data, r, d, eps, sigma2, 0.0,
+                                       U.ctypes.data, ctypes.byref(q)) == _lib.SK_OK
+    assert np.array_equal(U, inputs.gaussian_anchors(3, r, d, sigma2))
+    assert q.value == oracle.q_from_sigma2(sigma2, eps)
+
+
+@pytest.mark.parametrize("R,eps,d", [(4.0, 0.1, 3), (30.0, 10.0, 784), (1.0, 1.0, 128)])
+def test_gaussian_anchors_with_lambert_bandwidth(L, R, eps, d):
+    """sigma^2 from Lemma 1's q for the ball of radius R: q matches the
+    oracle's Lambert value and the anchors the oracle would draw from the
+    same normals (within one float32 rounding: q may differ in its last
+    bits between the two Lambert evaluations)."""
+    from paper_2006_07057_amd import inputs
+    r = 64
+    Z = inputs.standard_normal_anchors(5, r, d)
+    U = np.empty((r, d), np.float32)
+    q = ctypes.c_double()
+    assert L.sinkhorn_gaussian_anchors(Z.ctypes.data, r, d, eps, 0.0, R,
+                                       U.ctypes.data, ctypes.byref(q)) == _lib.SK_OK
+    qo = oracle.lambert_q(R, eps, d)
+    assert q.value == pytest.approx(qo, rel=1e-13)
+    Uo = inputs.gaussian_anchors(5, r, d, oracle.sigma2_from_q(qo, eps))
+    np.testing.assert_allclose(U, Uo, rtol=2 ** -23, atol=0)
+
+
+def test_new_entry_points_reject_bad_arguments(L):
+    P = ctypes.c_void_p(0x1000)
+    Z = np.zeros((4, 2))
+    U = np.empty((4, 2), np.float32)
+    q = ctypes.c_double()
+    f = L.sinkhorn_gaussian_anchors
+    assert f(None, 4, 2, 0.5, 1.0, 0.0, U.ctypes.data, ctypes.byref(q)) == _lib.SK_EINVAL
+    assert f(Z.ctypes.data, 0, 2, 0.5, 1.0, 0.0, U.ctypes.data, ctypes.byref(q)) == _lib.SK_EINVAL
+    assert f(Z.ctypes.data, 4, 2, 0.0, 1.0, 0.0, U.ctypes.data, ctypes.byref(q)) == _lib.SK_EINVAL
+    assert f(Z.ctypes.data, 4, 2, 0.5, 0.0, 0.0, U.ctypes.data, ctypes.byref(q)) == _lib.SK_EINVAL
+    assert f(Z.ctypes.data, 4, 2, 0.5, math.inf, 0.0, U.ctypes.data,
+             ctypes.byref(q)) == _lib.SK_EINVAL
+    assert L.sinkhorn_divergence_assemble(None, 1, P, None) == _lib.SK_EINVAL
+    assert L.sinkhorn_divergence_assemble(P, 0, P, None) == _lib.SK_EINVAL
+    assert L.sinkhorn_divergence_assemble(P, 1, None, None) == _lib.SK_EINVAL
+    o = _lib.sk_solve_opts(1e-6, 100, 0, 0, _lib.SK_RANGE_LINEAR)
+    p = _problem(r=7)                          # r + 1 = 8 columns
+    ws = L.sinkhorn_divergence_arccos_workspace_size(ctypes.byref(p))
+    assert ws > 0
+    lay = _lib.sk_state_layout()
+    assert L.sinkhorn_state_layout(10, 12, 8, ctypes.byref(lay)) == _lib.SK_OK
+    g = L.sinkhorn_divergence_arccos
+    assert g(ctypes.byref(_problem(r=8)), 1, 1.5, 0.5, ctypes.byref(o), P, P, lay.total,
+             P, ws, None) == _lib.SK_ENOTSUP   # 9 columns
+    assert g(ctypes.byref(p), 9, 1.5, 0.5, ctypes.byref(o), P, P, lay.total, P, ws,
+             None) == _lib.SK_EINVAL
+    assert g(ctypes.byref(p), 1, 1.0, 0.5, ctypes.byref(o), P, P, lay.total, P, ws,
+             None) == _lib.SK_EINVAL
+    assert g(ctypes.byref(p), 1, 1.5, 0.5, ctypes.byref(o), P, P, lay.total - 1, P, ws,
+             None) == _lib.SK_ENOMEM
+    assert g(ctypes.byref(p), 1, 1.5, 0.5, ctypes.byref(o), P, P, lay.total, P, ws - 1,
+             None) == _lib.SK_ENOMEM
+    ox = _lib.sk_solve_opts(1e-6, 100, 0, 0, _lib.SK_RANGE_EXTENDED)
+    assert g(ctypes.byref(p), 1, 1.5, 0.5, ctypes.byref(ox), P, P, lay.total, P, ws,
+             None) == _lib.SK_ENOTSUP

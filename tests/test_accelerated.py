@@ -9,6 +9,7 @@ import pytest
 
 import oracle
 from paper_2006_07057_amd import inputs
+from parity import check_divergence, check_gradient, check_value
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
 
@@ -252,7 +253,7 @@ def test_acc_fixed_steps_match_oracle(n, m, r, steps):
     K = Px @ Py.T if n * m <= 4_000_000 else None
     if K is not None:
         F = oracle.dual_value(ref.eta1, ref.eta2, K, a, b, 1.0)
-        assert info["w_hat"] == pytest.approx(F, rel=1e-5, abs=1e-6)
+        check_value(f"accelerated fixed-step dual value {n}x{m}", info["w_hat"], F)
 
 
 @pytest.mark.gpu
@@ -355,9 +356,7 @@ def test_acc_divergence_matches_converged_oracle(n, m, d, r, eps):
     meta = st.meta()
     assert meta[0] == 0 and np.all(meta[1:] >= infos["iters"])   # linear layout
     ref = oracle.divergence_scaled(X, Y, a, b, U, eps, q, tol=1e-11, max_iter=200000)
-    assert g[0] == pytest.approx(ref.value, rel=1e-5, abs=1e-7 * abs(ref.w_xy))
-    for k, w in enumerate((ref.w_xy, ref.w_xx, ref.w_yy)):
-        assert g[1 + k] == pytest.approx(w, rel=1e-5)
+    check_divergence(f"accelerated tol 1e-6 {n}x{m} d={d} r={r}", g, ref)
 
 
 @pytest.mark.gpu
@@ -390,12 +389,11 @@ def test_acc_divergence_gradients_match_oracle(seed, n, m, d, r, eps, steps):
         assert min(ms) > 1e-4, "oracle path has a near tie: pick another case"
         assert min(res.ls_margins) > 1e-2, "oracle path has a near tie: pick another case"
     assert list(st.meta()[1:]) == [rr.trials for rr in runs]
-    for k in range(4):
-        assert g[k] == pytest.approx(vals[k], rel=1e-5, abs=1e-7 * abs(vals[1]))
+    lab = f"accelerated {steps} steps {n}x{m} d={d} r={r}"
+    check_divergence(lab, g, vals)
     dX, da, dY, db = [t.cpu().numpy().astype(np.float64) for t in A.divergence_backward(st)]
-    for gg, rr in ((dX, rX), (da, ra), (dY, rY), (db, rb)):
-        rel = np.linalg.norm(gg - rr) / np.linalg.norm(rr)
-        assert rel <= 1e-4, rel
+    for nm, gg, rr in (("dX", dX, rX), ("da", da, ra), ("dY", dY, rY), ("db", db, rb)):
+        check_gradient(f"{lab} {nm}", gg, rr)
 
 
 @pytest.mark.gpu

@@ -8,8 +8,7 @@ import pytest
 
 import oracle
 from paper_2006_07057_amd import _lib, inputs
-
-DIV_RTOL = 1e-5
+from parity import check_divergence
 
 
 def test_arccos_argument_errors():
@@ -98,6 +97,6 @@ def test_arccos_divergence_matches_oracle(s, d):
         ws.append(oracle.w_hat_scaled(res.u, res.v, p, g, sp, sq, eps))
     ref = ws[0] - 0.5 * (ws[1] + ws[2])
     assert list(infos["status"]) == [0, 0, 0]
-    assert w_bar == pytest.approx(ref, rel=DIV_RTOL, abs=1e-7 * abs(ws[0]))
-    for k in range(3):
-        assert infos["w_hat"][k] == pytest.approx(ws[k], rel=DIV_RTOL)
+    check_divergence(f"arccos divergence s={s} d={d}",
+                     [w_bar] + [infos["w_hat"][k] for k in range(3)],
+                     (ref, ws[0], ws[1], ws[2]))

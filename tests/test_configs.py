@@ -1,5 +1,5 @@
 """Parity at the shapes of the remaining workloads (GPU): the
-differentiation workload shaped like the OT-GAN experiment of Sec. 5
+differentiation workload shaped like the OT-GAN experiment of Sec. 4
 (n = m = 8192 unit vectors in R^128, eps = 1, r = 2048) and the mixed batch
 of 256 pixel-like problems (d = 784, eps = 10, r in {512, 4096}) under the
 autotuner, at reduced point counts the float64 oracle can follow."""
@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 from paper_2006_07057_amd import inputs
+from parity import check_divergence, check_gradient, float32_wbar_floor
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
@@ -75,16 +76,15 @@ def test_otgan_shaped_gradients_and_descent(api):
     Px, sx = oracle.gaussian_features_scaled(c.X, U, eps, q)
     Py, sy = oracle.gaussian_features_scaled(c.Y, U, eps, q)
     ref = _oracle_div(c.X, c.Y, c.a, c.b, U, eps, q, (Px, sx, Py, sy))
-    assert g[0] == pytest.approx(ref.value, rel=1e-5, abs=1e-7 * abs(ref.w_xy))
+    check_divergence("otgan-shaped 8192 d=128 r=2048 step 0", g, ref)
     rX, ra, rY, rb = oracle.grads_from_scalings(
         c.X, c.Y, U, eps, Px, Py, (ref.xy.u, ref.xy.v), (ref.xx.u, ref.xx.v),
         (ref.yy.u, ref.yy.v))
     rng = np.random.default_rng(4)
     S = np.sort(rng.choice(n, 64, replace=False))
-    rel = np.linalg.norm(dX[S] - rX[S]) / np.linalg.norm(rX[S])
-    assert rel <= 1e-4, rel
-    for gg, rr in ((da, ra), (dY, rY), (db, rb)):
-        assert np.linalg.norm(gg - rr) <= 1e-4 * np.linalg.norm(rr)
+    check_gradient("otgan-shaped dX[64-point subsample]", dX[S], rX[S])
+    for nm, gg, rr in (("da", da, ra), ("dY", dY, rY), ("db", db, rb)):
+        check_gradient("otgan-shaped " + nm, gg, rr)
 
     # float64 central differences along directions supported on S
     X64 = c.X.astype(np.float64)
@@ -136,8 +136,11 @@ def test_otgan_shaped_gradients_and_descent(api):
     o, state = api.divergence(Xt, Y, a, b, Ud, eps, q, tol=1e-7, max_iter=2000)
     Pf, sf = oracle.gaussian_features_scaled(Xf, U, eps, q)
     reff = _oracle_div(Xf, c.Y, c.a, c.b, U, eps, q, (Pf, sf, Py, sy))
-    assert float(o[0].item()) == pytest.approx(reff.value, rel=1e-5,
-                                               abs=1e-7 * abs(reff.w_xy))
+    # after the descent W_bar (about 2e-5) is 1e-6 of the terms it is the
+    # difference of, so 1e-5 of it (2e-10) is below the float32 resolution
+    # of the dual sums: the float32 floor applies (derived in parity.py)
+    check_divergence("otgan-shaped after 50 steps", _host(o), reff,
+                     wbar_floor=float32_wbar_floor(eps, c.a, c.b))
 
 
 def test_mixed_pixel_batch_under_autotuner(api):
@@ -178,9 +181,9 @@ def test_mixed_pixel_batch_under_autotuner(api):
             _say("oracle problem", i, sizes[i])
             rX, ra, rY, rb, div = oracle.divergence_grad_scaled(cl.X, cl.Y, cl.a, cl.b, U,
                                                                 eps, q, tol=1e-12)
-            assert g[i, 0] == pytest.approx(div.value, rel=1e-5, abs=1e-7 * abs(div.w_xy))
+            lab = f"pixel batch problem {i} {sizes[i]}"
+            check_divergence(lab, g[i], div)
             dX = _host(api.divergence_backward(states[i])[0])
-            rel = np.linalg.norm(dX - rX) / np.linalg.norm(rX)
-            assert rel <= 1e-4, (i, rel)
+            check_gradient(lab + " dX", dX, rX)
     finally:
         autotune.reset()

@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 from paper_2006_07057_amd import inputs
+from parity import check_divergence
 
 HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
@@ -68,9 +69,8 @@ def test_gpu_gauss2d_matches_golden(rng_mode):
     out, _ = api.divergence(t(c.X), t(c.Y), t(c.a), t(c.b), t(U), g["eps"], g["q"],
                             fixed_iter=g["fixed_iter"], range=rng_mode)
     o = out.cpu().numpy()
-    assert o[0] == pytest.approx(g["W_bar"], rel=1e-5)
-    for k, key in enumerate(("W_xy", "W_xx", "W_yy")):
-        assert o[1 + k] == pytest.approx(g[key], rel=1e-5, abs=1e-6)
+    check_divergence(f"golden gauss2d_1k range={rng_mode}", o,
+                     (g["W_bar"], g["W_xy"], g["W_xx"], g["W_yy"]))
 
 
 @pytest.mark.gpu
