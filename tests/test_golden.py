@@ -96,3 +96,37 @@ def test_gpu_accelerated_matches_golden():
     assert rec["status"] == 0 and rec["iters"] == g["steps"]
     assert int(tr.cpu()[0]) == g["trials"]
     assert rec["w_hat"] == pytest.approx(g["dual_value"], rel=1e-5)
+
+
+@pytest.mark.gpu
+def test_gpu_gmm3d_1m_matches_golden():
+    """The 10^6-point mixture workload at full size (two 4-component Gaussian
+    mixtures in R^3, r = 1024, eps = 0.1), inputs and anchors made as the
+    benchmark makes them, through the entry point and launch the benchmark
+    times, against the factored float64 oracle's stored values: 100 fixed
+    iterations (every term and W_bar within 1e-5), and the stop test at
+    tol = 1e-6 with at most 2000 iterations (W_bar and the terms within
+    1e-5; iteration counts within the float32 jitter of the stopping index
+    near the tolerance)."""
+    import torch
+    from paper_2006_07057_amd import api
+    g = _load("gmm3d_1m")
+    c = inputs.gmm3d(0)
+    U, q = api.gaussian_anchors(inputs.standard_normal_anchors(0, 1024, 3), 0.1,
+                                R=inputs.max_norm(c.X, c.Y))
+    assert q == pytest.approx(g["q"], rel=1e-13)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    X, Y, a, b, Ud = t(c.X), t(c.Y), t(c.a), t(c.b), t(U)
+    for key, kw in (("fixed_100", dict(fixed_iter=100)),
+                    ("tol_1e-6", dict(tol=1e-6, max_iter=2000))):
+        ref = g[key]
+        out, st = api.divergence(X, Y, a, b, Ud, 0.1, q, **kw)
+        o = out.cpu().numpy()
+        infos = st.infos()
+        print(f"[golden] gmm3d_1m {key}: iters gpu {list(infos['iters'])} "
+              f"oracle {ref['iters']}", flush=True)
+        assert list(infos["status"]) == [0, 0, 0]
+        check_divergence(f"gmm3d_1m {key}", o,
+                         (ref["W_bar"], ref["W_xy"], ref["W_xx"], ref["W_yy"]))
+        for it, rit in zip(infos["iters"], ref["iters"]):
+            assert abs(int(it) - rit) <= max(3, rit // 20), (key, it, rit)
