@@ -204,6 +204,28 @@ int sinkhorn_solve(const float* Phix, int64_t n, const float* Phiy, int64_t m,
                    float* z, sk_solve_info* info, void* ws, size_t ws_bytes,
                    sk_stream_t stream);
 
+/* Allocation-free variant of sinkhorn_solve, for callers that cannot
+ * allocate device memory or pass a workspace (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).
+ * Arguments, outputs and results are those of sinkhorn_solve (the same
+ * kernels run with the same launch plan, so results are identical); the
+ * scratch space comes from a static device array of
+ * SK_NOALLOC_SCRATCH_BYTES held by each device the library runs on until
+ * the process ends, and the call allocates nothing.  Sizes whose workspace
+ * (sinkhorn_solve_workspace_size) exceeds it are rejected with SK_ENOMEM:
+ * with n = m, r <= 1024 fits up to about 6.2e6 points per side, r = 2048
+ * up to 4.1e6, r = 4096 only up to 3.2e4.  Every call on one device shares that
+ * device's array: calls that overlap on one device (two streams, two host
+ * threads) race and must not be issued.
+ * Errors: as sinkhorn_solve, plus SK_ENOMEM (scratch too small), SK_EHIP
+ * (the array's device address could not be obtained), SK_ENOTSUP (device
+ * index >= 64). */
+#define SK_NOALLOC_SCRATCH_BYTES (64u << 20)
+int sinkhorn_solve_noalloc(const float* Phix, int64_t n, const float* Phiy, int64_t m,
+                           int64_t r, const float* a, const float* b,
+                           const sk_solve_opts* opts, float* u, float* v, float* w,
+                           float* z, sk_solve_info* info, sk_stream_t stream);
+
 /* ------------------------------------------------------------------ (a5) */
 /* One divergence problem: points, weights and the feature map. */
 typedef struct {

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libsinkhorn.so")
 SK_OK, SK_EINVAL, SK_ENOMEM, SK_ERANGE, SK_ENOTCONV, SK_EHIP, SK_ETIMEOUT, \
     SK_ENOTSUP = range(8)
 SK_MAX_R = 4096
+SK_NOALLOC_SCRATCH_BYTES = 64 << 20
 SK_RANGE_EXTENDED, SK_RANGE_LINEAR = 0, 1
 
 c_i32, c_i64, c_f32p, c_dbl = ctypes.c_int32, ctypes.c_int64, \
@@ -67,6 +68,9 @@ SIGNATURES = {
                                c_void, ctypes.POINTER(sk_solve_opts), c_void,
                                c_void, c_void, c_void, c_void, c_void, c_size,
                                c_void]),
+    "sinkhorn_solve_noalloc": (c_i32, [c_void, c_i64, c_void, c_i64, c_i64, c_void,
+                                       c_void, ctypes.POINTER(sk_solve_opts), c_void,
+                                       c_void, c_void, c_void, c_void, c_void]),
     "sinkhorn_state_layout": (c_i32, [c_i64, c_i64, c_i64,
                                       ctypes.POINTER(sk_state_layout)]),
     "sinkhorn_divergence_workspace_size": (c_size, [ctypes.POINTER(sk_problem)]),

@@ -7,11 +7,39 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <vector>
 
 using namespace sk;
 
+// Static device scratch of sinkhorn_solve_noalloc (one copy per device,
+// held until the process ends).  In host code `scratch` names a host-side
+// stand-in, never device memory: its device address is taken once per
+// device with hipGetSymbolAddress and only that address is used.
+constexpr size_t kNoAllocScratchBytes = (size_t)SK_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the
+// first call on that device, with that device current).
+int noalloc_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return SK_EHIP;
+  if (dev >= kMaxDevices) return SK_ENOTSUP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SK_EHIP;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return SK_OK;
+}
 
 inline hipStream_t S(sk_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -495,6 +523,32 @@ int sinkhorn_solve(const float* Phix, int64_t n, const float* Phiy, int64_t m,
   std::vector<SolveSpec> specs{sp};
   size_t need = 0;
   return run_solves(specs, opts, ws, ws_bytes, &need, S(stream));
+}
+
+int sinkhorn_solve_noalloc(const float* Phix, int64_t n, const float* Phiy, int64_t m,
+                           int64_t r, const float* a, const float* b,
+                           const sk_solve_opts* opts, float* u, float* v, float* w,
+                           float* z, sk_solve_info* info, sk_stream_t stream) {
+  if (!Phix || !Phiy || !a || !b || !u || !v || !w || !z || !info) return SK_EINVAL;
+  if (n < 1 || m < 1 || r < 1) return SK_EINVAL;
+  if (r > SK_MAX_R || r % 4 != 0) return SK_ENOTSUP;
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  SolveSpec sp;
+  sp.Prow = Phix; sp.Pcol = Phiy; sp.a = a; sp.b = b;
+  sp.srow = nullptr; sp.scol = nullptr;
+  sp.u = u; sp.v = v; sp.w = w; sp.z = z; sp.info = info;
+  sp.n = n; sp.m = m; sp.r = (int)r; sp.eps = 1.0;
+  std::vector<SolveSpec> specs{sp};
+  size_t need = 0;
+  run_solves(specs, opts, nullptr, 0, &need, nullptr);
+  if (need > kNoAllocScratchBytes) return SK_ENOMEM;
+  void* ws = nullptr;
+  rc = noalloc_scratch(&ws);
+  if (rc) return rc;
+  // every piece of the workspace that must start at zero (launch control
+  // block, barrier counters) is cleared by the launch sequence itself
+  return run_solves(specs, opts, ws, kNoAllocScratchBytes, &need, S(stream));
 }
 
 size_t sinkhorn_solve_batched_workspace_size(const sk_solve_spec* specs,
