@@ -352,6 +352,52 @@ def test_gradients_match_finite_differences():
     assert abs(da.sum()) < 1e-12 and abs(db.sum()) < 1e-12
 
 
+def _frozen_value(X, Y, a, b, U, eps, q, sc):
+    """The dual estimates' combination with the scalings of the three solves
+    frozen at sc = ((u_xy, v_xy), (u_xx, v_xx), (u_yy, v_yy)): for one solve
+    on K = Phi_r Phi_c^T with weights (p, g),
+        D = eps (p^T log u + g^T log v) - eps u^T K v,
+    the dual objective of Eq. (eval-dual) written with the scalings (its
+    value at a Sinkhorn iterate is the dual estimate plus the constant
+    -eps u^T K v = -eps).  Returns D_xy - (D_xx + D_yy) / 2."""
+    Px = oracle.gaussian_features(X, U, eps, q)
+    Py = oracle.gaussian_features(Y, U, eps, q)
+    out = 0.0
+    for (P, Q, p, g), (u, v), c in zip(((Px, Py, a, b), (Px, Px, a, a), (Py, Py, b, b)),
+                                       sc, (1.0, -0.5, -0.5)):
+        out += c * eps * (p @ np.log(u) + g @ np.log(v) - u @ (P @ (Q.T @ v)))
+    return out
+
+
+def test_fixed_iteration_gradients_are_frozen_scaling_derivatives():
+    """Off convergence (5 iterations, where the two sides of a self-problem
+    still differ: u_xx != v_xx), the gradient readings the GPU is compared
+    with at fixed iteration counts (both sides of the self terms, weight
+    gradient eps(log u_xy - (log u_xx + log v_xx)/2)) are exactly the
+    derivatives of the dual objective with the iterates' scalings held
+    fixed (Prop. 3.2's envelope form dW/dK = -eps u v^T applied at those
+    scalings).  Central differences of that frozen function in X, Y, U and
+    along simplex directions of a, b pin the formulas at any iteration
+    count; using one side twice, or dropping log v_xx, fails here."""
+    X, Y, a, b, U, eps, q = _small_problem(19, 7, 6, r=9, eps=0.7)
+    dX, da, dY, db, div = oracle.divergence_grad(X, Y, a, b, U, eps, q, fixed_iter=5)
+    sc = ((div.xy.u, div.xy.v), (div.xx.u, div.xx.v), (div.yy.u, div.yy.v))
+    assert np.max(np.abs(np.log(div.xx.u / div.xx.v))) > 1e-3   # really off convergence
+    f = lambda **kw: _frozen_value(kw.get("X", X), kw.get("Y", Y), kw.get("a", a),
+                                   kw.get("b", b), kw.get("U", U), eps, q, sc)
+    np.testing.assert_allclose(dX, _fd(lambda Z: f(X=Z), X, 1e-5), rtol=1e-7, atol=1e-10)
+    np.testing.assert_allclose(dY, _fd(lambda Z: f(Y=Z), Y, 1e-5), rtol=1e-7, atol=1e-10)
+    dU, _ = oracle.divergence_grad_anchors(X, Y, a, b, U, eps, q, fixed_iter=5)
+    np.testing.assert_allclose(dU, _fd(lambda Z: f(U=Z), U, 1e-5), rtol=1e-7, atol=1e-10)
+    h = 1e-3      # the frozen function is linear in the weights
+    for wts, grad, key in ((a, da, "a"), (b, db, "b")):
+        for i, j in [(0, 1), (2, 4), (5, 3)]:
+            e = np.zeros(len(wts))
+            e[i], e[j] = 1.0, -1.0
+            fd = (f(**{key: wts + h * e}) - f(**{key: wts - h * e})) / (2 * h)
+            assert grad @ e == pytest.approx(fd, rel=1e-9, abs=1e-12), (key, i, j)
+
+
 def test_scaled_gradient_equals_unscaled_and_fd_at_large_d():
     """divergence_grad_scaled equals divergence_grad where raw features are
     representable, and at d = 128 (raw features below float64 range for
