@@ -101,6 +101,7 @@ std::map<int, int64_t>& tuning_table() {
 int class_rmax(int r) { return solver_class_rmax(r); }
 
 constexpr int64_t kDefaultTarget = 256 * 1024;
+constexpr int64_t kMaxRowsPerLane = 256;            // see run_solves
 constexpr int64_t kSideBySideBytes = 256ll << 20;   // feature bytes per iteration
 
 int planned_group(int64_t n, int64_t m, int r) {
@@ -111,6 +112,9 @@ int planned_group(int64_t n, int64_t m, int r) {
   const int64_t rows = n > m ? n : m;
   const int64_t bytes = rows * (int64_t)r * 4;
   int64_t g = (bytes + target - 1) / target;
+  // precision floor (see run_solves): at most kMaxRowsPerLane rows per lane
+  const int64_t per_wg = kMaxRowsPerLane * (int64_t)kBlock / std::max(solver_class_lanes(r), 1);
+  g = std::max<int64_t>(g, (rows + per_wg - 1) / per_wg);
   if (g < 1) g = 1;
   if (g > kMaxGroup) g = kMaxGroup;
   // no more workgroups than row chunks of one wave-load each
@@ -218,6 +222,21 @@ int run_solves(const std::vector<SolveSpec>& specs, const sk_solve_opts* o,
     } else {
       for (int i : order) gshare[i] = gplan[i];
     }
+    // Precision floor: each lane sums the transposed products of its rows
+    // in float32, one after the other, so the rounding error of an r-vector
+    // entry grows with the rows a lane adds (about sqrt(rows) units of
+    // 2^-24).  That error changes from one iteration to the next and puts a
+    // floor under the stop test's marginal error: a solve packed into a
+    // small gang (two workgroups for 2e5 rows) stalled near 1e-6.  Every
+    // gang is therefore large enough that no lane adds more than
+    // kMaxRowsPerLane rows per half-step.
+    const int lanes = solver_class_lanes(rmax);
+    for (int i : order) {
+      const int64_t rows = std::max(specs[i].n, specs[i].m);
+      const int64_t per_wg = kMaxRowsPerLane * (int64_t)kBlock / std::max(lanes, 1);
+      const int64_t gmin = (rows + per_wg - 1) / per_wg;   // <= gplan[i] by planning
+      gshare[i] = (int)std::max<int64_t>(gshare[i], std::min<int64_t>(gmin, gplan[i]));
+    }
     std::vector<SolveDesc> descs(order.size());
     int seat = 0;
     int64_t moff = 0;
@@ -250,7 +269,7 @@ int run_solves(const std::vector<SolveSpec>& specs, const sk_solve_opts* o,
     SK_HIP(upload_descs(cb.descs, descs.data(), (int)descs.size(), s));
     SK_HIP(launch_init_ctl(cb.ctl, cb.bars, (int)descs.size(), s));
     SK_HIP(launch_solver(cb.descs, (int)descs.size(), rmax, xr, seat, grid,
-                         cb.ctl, s));
+                         cb.ctl, cb.bars, s));
   }
   return SK_OK;
 }
@@ -847,9 +866,9 @@ int sinkhorn_divergence_batched(const sk_problem* problems, int32_t count,
     sk_state_layout L;
     layout_of(p.n, p.m, p.r, &L);
     FeatDesc fx{p.X, p.U, at<float>(states[i], L.phix), at<float>(states[i], L.sx),
-                p.n, (int32_t)p.d, (int32_t)p.r, (float)p.eps, (float)p.q, xr, 0, 0};
+                p.n, (int32_t)p.d, (int32_t)p.r, p.eps, p.q, xr, 0, 0};
     FeatDesc fy{p.Y, p.U, at<float>(states[i], L.phiy), at<float>(states[i], L.sy),
-                p.m, (int32_t)p.d, (int32_t)p.r, (float)p.eps, (float)p.q, xr, 0, 0};
+                p.m, (int32_t)p.d, (int32_t)p.r, p.eps, p.q, xr, 0, 0};
     fgroups[class_rmax((int)p.r)].push_back(fx);
     fgroups[class_rmax((int)p.r)].push_back(fy);
   }

@@ -73,23 +73,25 @@ features_kernel(const FeatDesc* __restrict__ descs, int count, FeatDesc one,
         }
       }
       __syncthreads();
-      const float eps = D.eps, q = D.q;
-      neg2e = -2.0f / eps;
-      const float cst = -0.5f * logf((float)r) + 0.25f * (float)d * logf(2.0f * q);
-      const float inv_eq = 1.0f / (eps * q);
+      const double eps = D.eps, q = D.q;
+      neg2e = (float)(-2.0 / eps);
+      // c_k = -log(r)/2 + (d/4) log(2q) + ||u_k||^2 / (eps q), formed in
+      // float64 and rounded once
+      const double cst = -0.5 * log((double)r) + 0.25 * (double)d * log(2.0 * q);
+      const double inv_eq = 1.0 / (eps * q);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
           const int col = VEC * cl + VEC * G * c + v;
-          float un = 0.f;
+          double un = 0.0;
           if (col < r) {
             for (int dim = 0; dim < d; ++dim) {
-              const float uk = in_lds ? Ut[dim * rp + col] : D.U[(int64_t)col * d + dim];
-              un = fmaf(uk, uk, un);
+              const double uk = in_lds ? Ut[dim * rp + col] : D.U[(int64_t)col * d + dim];
+              un = fma(uk, uk, un);
             }
           }
-          cval[c][v] = fmaf(un, inv_eq, cst);
+          cval[c][v] = (float)fma(un, inv_eq, cst);
         }
       }
     }
@@ -207,29 +209,15 @@ constexpr int kMfmaCols = 64;
 constexpr int kMfmaK = 32;
 constexpr int kMfmaPad = 36;  // floats per LDS row (bank spread)
 
-// c_k of the columns, written by anchor_cval_kernel before each MFMA launch
+// c_k of the columns, written by anchor_cterm_kernel before each MFMA launch
 // (launches on one device run one after another on their stream).
 __device__ float g_anchor_cval[SK_MAX_R];
 
-// One wave per anchor: lanes take coordinates e = lane, lane + 64, ...
-// (coalesced), then a butterfly in a fixed order.
-__global__ void __launch_bounds__(kBlock)
-anchor_cval_kernel(const float* __restrict__ U, int r, int d, float c0, float cu) {
-  const int k = blockIdx.x * kWaves + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (k >= r) return;   // whole waves leave together
-  double un = 0.0;
-  for (int e = lane; e < d; e += 64) {
-    const double v = U[(int64_t)k * d + e];
-    un += v * v;
-  }
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) un += __shfl_xor(un, off, 64);
-  if (lane == 0) g_anchor_cval[k] = fmaf(cu, (float)un, c0);
-}
-
-// Arc-cosine variant of the anchor terms, c0 + cu ||u_k||^2 formed in
-// float64 and rounded once.
+// Anchor terms c_k = c0 + cu ||u_k||^2 (Gaussian map: c0 = -log(r)/2 +
+// (d/4) log(2q), cu = 1/(eps q) - 2/eps; arc-cosine map: its own c0, cu),
+// formed in float64 and rounded once.  One wave per anchor: lanes take
+// coordinates e = lane, lane + 64, ... (coalesced), then a butterfly in a
+// fixed order.
 __global__ void __launch_bounds__(kBlock)
 anchor_cterm_kernel(const float* __restrict__ U, int r, int d, double c0, double cu) {
   const int k = blockIdx.x * kWaves + (threadIdx.x >> 6);
@@ -457,11 +445,11 @@ hipError_t launch_mfma(const FeatDesc& D, hipStream_t s, const FeatDesc* D2 = nu
   float* s2 = D2 ? D2->s : nullptr;
   const double eps = D.eps, q = D.q;
   if (D.r > SK_MAX_R || D.r % 4 != 0) return hipErrorInvalidValue;
-  const float c0 = (float)(-0.5 * log((double)D.r) + 0.25 * D.d * log(2.0 * q));
-  const float cu = (float)(1.0 / (eps * q) - 2.0 / eps);
+  const double c0 = -0.5 * log((double)D.r) + 0.25 * D.d * log(2.0 * q);
+  const double cu = 1.0 / (eps * q) - 2.0 / eps;
   const float scale = (float)(4.0 / eps);
   const float neg2e = (float)(-2.0 / eps);
-  hipLaunchKernelGGL(anchor_cval_kernel, dim3((D.r + kWaves - 1) / kWaves), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL(anchor_cterm_kernel, dim3((D.r + kWaves - 1) / kWaves), dim3(kBlock), 0, s,
                      D.U, D.r, D.d, c0, cu);
   const hipError_t e0 = hipGetLastError();
   if (e0 != hipSuccess) return e0;
@@ -665,7 +653,7 @@ hipError_t launch_features(const float* X, int64_t n, int d, const float* U,
   FeatDesc one{};
   one.X = X; one.U = U; one.Phi = Phi; one.s = logscale;
   one.n = n; one.d = d; one.r = r;
-  one.eps = (float)eps; one.q = (float)q; one.tile0 = 0;
+  one.eps = eps; one.q = q; one.tile0 = 0;
   one.log2_out = log2_out;
   void* tok = prof_begin(kProfFeatures, s);
   hipError_t e;
@@ -694,7 +682,7 @@ hipError_t launch_features_pair(const float* X, int64_t n, const float* Y, int64
   dx.X = X; dx.U = U; dx.Phi = PhiX; dx.s = sX; dx.n = n;
   dy.X = Y; dy.U = U; dy.Phi = PhiY; dy.s = sY; dy.n = m;
   for (FeatDesc* f : {&dx, &dy}) {
-    f->d = d; f->r = r; f->eps = (float)eps; f->q = (float)q; f->tile0 = 0;
+    f->d = d; f->r = r; f->eps = eps; f->q = q; f->tile0 = 0;
     f->log2_out = log2_out;
   }
   void* tok = prof_begin(kProfFeatures, s);

@@ -64,6 +64,10 @@ constexpr int kMaxGroup = 2048;
 // Largest r of the solver class that handles feature count r (0 if none).
 int solver_class_rmax(int r);
 
+// Lanes per feature row of that class (each workgroup's kBlock threads
+// cover kBlock / lanes rows at a time; 0 if none).
+int solver_class_lanes(int r);
+
 // Maximum number of co-resident workgroups of the solver for feature
 // count r (xr != 0: extended-range kernels) on the current device (0 on
 // error).
@@ -82,8 +86,11 @@ hipError_t upload_descs(SolveDesc* dev, const SolveDesc* host, int count,
 
 // Run all solves in `dev_descs` (count entries, all with the same r class
 // and numeric domain) in one persistent launch.  total_seats = sum of g.
+// In the extended range a second launch follows, which resumes only the
+// solves the first left for it (see solve.hip); bars (count counters) are
+// cleared again for it.
 hipError_t launch_solver(const SolveDesc* dev_descs, int count, int r, int xr,
-                         int total_seats, int grid, LaunchCtl* ctl,
+                         int total_seats, int grid, LaunchCtl* ctl, unsigned* bars,
                          hipStream_t s);
 
 // Features (row-scaled Gaussian positive features; log2 values when
@@ -100,7 +107,8 @@ struct FeatDesc {
   float* s;
   int64_t n;
   int32_t d, r;
-  float eps, q;
+  double eps, q;         // exact parameters: the per-anchor constants are
+                         // formed from them in float64 and rounded once
   int32_t log2_out;
   int32_t pad;
   int64_t tile0;         // first row-tile index of this problem

@@ -53,6 +53,15 @@ constexpr float kNegBig = -1.0e30f;   // "log of zero" sentinel (finite)
 // Weights must be probability vectors with positive entries (Sec. 2: a in
 // the simplex); their sum is checked in float64 to this tolerance.
 constexpr double kWeightSumTol = 1e-5;
+// A framed sum below this (relative to its column frame) may have lost
+// terms to float32 underflow: the solve then accumulates with per-column
+// exponents from that half-step on (see run_solve).
+constexpr float kFrameFloor = 7.8886091e-31f;   // 2^-100
+// Internal solve states left in sk_solve_info.status by the fast kernel for
+// the robust one (never returned to callers: the robust kernel overwrites
+// them): resume at the v-pass or at the u-pass of iteration info.iters.
+constexpr int kResumeV = 101;
+constexpr int kResumeU = 102;
 
 __device__ __forceinline__ float4 f4zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
 __device__ __forceinline__ float4 f4fill(float v) { return make_float4(v, v, v, v); }
@@ -71,6 +80,24 @@ __device__ __forceinline__ float f4dot(const float4& a, const float4& b, float t
   t = fmaf(a.w, b.w, t);
   return t;
 }
+
+// Compensated float32 summation (Knuth's TwoSum: s + x = t + e exactly).
+// The cross-workgroup reductions of the r-vectors add hundreds of partial
+// sums per column; summed plainly, their rounding error (a few 1e-7
+// relative) changes from one iteration to the next and sets a floor under
+// the marginal error of the stop test.  Carrying the rounding error keeps
+// each reduced entry within about one float32 rounding of the exact sum of
+// its partials, in float32 arithmetic only.
+struct CSum {
+  float s = 0.f, c = 0.f;
+  __device__ __forceinline__ void add(float x) {
+    const float t = s + x;
+    const float bp = t - s;
+    c += (s - (t - bp)) + (x - bp);
+    s = t;
+  }
+  __device__ __forceinline__ float value() const { return s + c; }
+};
 
 __device__ __forceinline__ float xexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float xldexp(float m, float e) {
@@ -335,7 +362,7 @@ struct LinearDomain {
   }
 
   // sold/snew/target index rows; scalings are single floats.
-  template <int MODE>
+  template <int MODE, bool ROBUST>
   __device__ __forceinline__ static void half_step(const float* __restrict__ P, int64_t lo,
                                    int64_t hi, int r, int64_t nrows,
                                    State& S, const float* __restrict__ target,
@@ -451,7 +478,7 @@ struct LinearDomain {
   // Sum the per-lane accumulators of the workgroup into out (r floats).
   template <bool FRAMED>
   __device__ __forceinline__ static void block_store(State& S, float* __restrict__ out, int r,
-                                                     float* ldsf, const float*, bool) {
+                                                     float* ldsf, const float*, bool, int*) {
     float4* lds = reinterpret_cast<float4*>(ldsf);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -495,7 +522,7 @@ struct LinearDomain {
                                                        const int32_t* __restrict__ members,
                                                        int g, int r, int br,
                                                        float* __restrict__ out, float* ldsf,
-                                                       const float*) {
+                                                       const float*, int*) {
     float4* lds = reinterpret_cast<float4*>(ldsf);
     const int r4 = r >> 2;
     const int per = (r4 + g - 1) / g;
@@ -507,23 +534,35 @@ struct LinearDomain {
       const int t = threadIdx.x;
       const int col = cc + t % nc;
       const int split = t / nc;
-      float4 s = f4zero();
+      CSum sx, sy, sz, sw;
       if (split < Sn) {
         for (int b = split; b < g; b += Sn) {
           const float4 v =
               cld4(slots + (int64_t)cld(members + b) * slot_stride + 4 * col);
-          s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+          sx.add(v.x); sy.add(v.y); sz.add(v.z); sw.add(v.w);
         }
       }
-      lds[t] = s;
+      // combine the Sn splits: their sums, then their carried errors
+      lds[t] = make_float4(sx.s, sy.s, sz.s, sw.s);
+      __syncthreads();
+      CSum tx, ty, tz, tw;
+      if (t < nc) {
+        for (int k = 0; k < Sn; ++k) {
+          const float4 v = lds[t + k * nc];
+          tx.add(v.x); ty.add(v.y); tz.add(v.z); tw.add(v.w);
+        }
+      }
+      __syncthreads();
+      lds[t] = make_float4(sx.c, sy.c, sz.c, sw.c);
       __syncthreads();
       if (t < nc) {
-        float4 tot = lds[t];
-        for (int k = 1; k < Sn; ++k) {
+        float4 e = f4zero();
+        for (int k = 0; k < Sn; ++k) {
           const float4 v = lds[t + k * nc];
-          tot.x += v.x; tot.y += v.y; tot.z += v.z; tot.w += v.w;
+          e.x += v.x; e.y += v.y; e.z += v.z; e.w += v.w;
         }
-        cst4(out + 4 * col, tot);
+        cst4(out + 4 * col, make_float4(tx.s + (tx.c + e.x), ty.s + (ty.c + e.y),
+                                        tz.s + (tz.c + e.z), tw.s + (tw.c + e.w)));
       }
       __syncthreads();
     }
@@ -656,7 +695,7 @@ struct XRangeDomain {
 
   // sold: [E(nrows) | M(nrows)] previous scaling (CHECK modes) or warm
   // start (ACCUM); snew: [E | M] new scaling.  target: linear weights.
-  template <int MODE>
+  template <int MODE, bool ROBUST>
   __device__ __forceinline__ static void half_step(const float* __restrict__ P, int64_t lo,
                                    int64_t hi, int r, int64_t nrows, State& S,
                                    const float* __restrict__ target,
@@ -769,9 +808,15 @@ struct XRangeDomain {
               gst(snew + nrows + row, nm);
             }
           }
-          const float coef = rv ? nm : 0.0f;
+          if (ROBUST) {
+            // pairs with a per-column running exponent (as the first pass):
+            // the new entry k is sum_rows nm 2^(L_k - mx), whatever its range
+            accum_row(S, B.x[uu], rv ? -mx : kNegBig, rv ? nm : 0.f, rv, started);
+          } else {
+            const float coef = rv ? nm : 0.0f;
 #pragma unroll
-          for (int c = 0; c < C; ++c) f4fma(S.accM[c], coef, e[c]);
+            for (int c = 0; c < C; ++c) f4fma(S.accM[c], coef, e[c]);
+          }
         } else {
           if (rv && !(ssum > 0.0f)) bad = 1;
         }
@@ -820,7 +865,7 @@ struct XRangeDomain {
   template <bool FRAMED>
   __device__ __forceinline__ static void block_store(State& S, float* __restrict__ out, int r,
                                                      float* lds, const float* frame,
-                                                     bool final) {
+                                                     bool final, int* uflow) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (FRAMED) {
@@ -849,6 +894,7 @@ struct XRangeDomain {
         for (int w = 1; w < kWaves; ++w) s += lds[w * r + col];
         if (final) {
           float E, M;
+          if (s < kFrameFloor && cld(frame + r + col) > 0.f) *uflow = 1;
           frame_to_pair(s, cld(frame + col), E, M);
           cst(out + col, E);
           cst(out + r + col, M);
@@ -909,7 +955,7 @@ struct XRangeDomain {
                                                        const int32_t* __restrict__ members,
                                                        int g, int r, int br,
                                                        float* __restrict__ out, float* lds,
-                                                       const float* frame) {
+                                                       const float* frame, int* uflow) {
     const int per = (r + g - 1) / g;
     const int c0 = br * per;
     const int c1 = min(r, c0 + per);
@@ -920,29 +966,40 @@ struct XRangeDomain {
       const int col = cc + t % nc;
       const int split = t / nc;
       float e = kNegBig, m = 0.f;
+      CSum fs;   // framed sums: compensated
       if (split < Sn) {
         for (int b = split; b < g; b += Sn) {
           const float* p = slots + (int64_t)cld(members + b) * slot_stride;
           if (FRAMED) {
-            m += cld(p + col);
+            fs.add(cld(p + col));
           } else {
             xr_combine(e, m, cld(p + col), cld(p + r + col));
           }
         }
+      }
+      if (FRAMED) {
+        e = fs.c;   // the carried error travels in the exponent slot
+        m = fs.s;
       }
       lds[t] = e;
       lds[kBlock + t] = m;
       __syncthreads();
       if (t < nc) {
         float te = lds[t], tm = lds[kBlock + t];
-        for (int k = 1; k < Sn; ++k) {
-          if (FRAMED) {
-            tm += lds[kBlock + t + k * nc];
-          } else {
-            xr_combine(te, tm, lds[t + k * nc], lds[kBlock + t + k * nc]);
+        if (FRAMED) {
+          CSum ts;
+          float ec = 0.f;
+          for (int k = 0; k < Sn; ++k) {
+            ts.add(lds[kBlock + t + k * nc]);
+            ec += lds[t + k * nc];
           }
+          tm = ts.s + (ts.c + ec);
+        }
+        for (int k = 1; k < Sn; ++k) {
+          if (!FRAMED) xr_combine(te, tm, lds[t + k * nc], lds[kBlock + t + k * nc]);
         }
         if (FRAMED) {
+          if (tm < kFrameFloor && cld(frame + r + col) > 0.f) *uflow = 1;
           frame_to_pair(tm, cld(frame + col), te, tm);
         } else if (tm > 0.f) {  // normalise the mantissa to [0.5, 1)
           int ex = 0;
@@ -981,16 +1038,20 @@ template <class Dom, bool FRAMED>
 __device__ __forceinline__ bool finish_half_step(
     const SolveDesc& D, int br, BarrierState& B, typename Dom::State& S,
     float* __restrict__ dst, bool reduce_vec, const float* frame, double& err,
-    int& bad, float* lds, Shared& sh) {
+    int& bad, int& uflow, float* lds, Shared& sh) {
+  __shared__ int s_uflow;
   const int g = D.g;
   const double e_blk = block_dsum(err, sh.d);
   const double b_blk = block_dsum((double)bad, sh.d);
+  if (threadIdx.x == 0) s_uflow = 0;
+  __syncthreads();
   if (reduce_vec) {
     if (g == 1) {
-      Dom::template block_store<FRAMED>(S, dst, D.r, lds, frame, true);
+      Dom::template block_store<FRAMED>(S, dst, D.r, lds, frame, true, &s_uflow);
     } else {
       Dom::template block_store<FRAMED>(
-          S, D.slots + (int64_t)blockIdx.x * D.slot_stride, D.r, lds, frame, false);
+          S, D.slots + (int64_t)blockIdx.x * D.slot_stride, D.r, lds, frame, false,
+          &s_uflow);
     }
   }
   if (threadIdx.x == 0) {
@@ -1001,13 +1062,18 @@ __device__ __forceinline__ bool finish_half_step(
   if (g > 1) {
     if (reduce_vec)
       Dom::template column_reduce<FRAMED>(D.slots, D.slot_stride, D.members, g, D.r,
-                                          br, dst, lds, frame);
+                                          br, dst, lds, frame, &s_uflow);
+    __syncthreads();
+    if (FRAMED && threadIdx.x == 0) cst(D.dpart + 5 * g + br, (double)s_uflow);
     err = group_dsum(D.dpart, g, sh.d);
     bad = group_dsum(D.dpart + g, g, sh.d) > 0.0 ? 1 : 0;
     if (!group_barrier(B)) return false;
+    uflow = (FRAMED && reduce_vec) ? (group_dsum(D.dpart + 5 * g, g, sh.d) > 0.0 ? 1 : 0) : 0;
   } else {
     err = e_blk;
     bad = b_blk > 0.0 ? 1 : 0;
+    __syncthreads();
+    uflow = (FRAMED && reduce_vec) ? s_uflow : 0;
   }
   return true;
 }
@@ -1030,10 +1096,174 @@ __device__ __forceinline__ int uniform_i32(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
+// ------------------------------------------------ dual objective at the end
+// The dual estimate eps (a^T log u + b^T log v) equals the dual objective of
+// Eq. (eval-dual) only where u^T K v = 1, which an exact u-update makes
+// true.  With float32 scalings it holds to about 1e-7, and that residual
+// enters the estimate at first order, while the objective itself
+//   eps (a^T log u + b^T log v) - eps (u^T K v - 1)
+// is stationary at the optimum, so rounding of the scalings enters it at
+// second order.  Between divergence terms of similar size (two samples of
+// one distribution) the first-order part dominates W_bar.  The final phase
+// therefore evaluates u^T K v = (Prow^T u) . (Pcol^T v) once more, in
+// float64 from the stored features and scalings: z64 = Prow^T u (per
+// column, relative to the frame 2^zE of the float32 z in the extended
+// range), then sum_j v_j (Pcol_j . z64).
+
+// z64 partial of one workgroup over its rows [lo, hi) of Prow, written to
+// its slot as r doubles.  Thread t owns columns t, t + kBlock, ...
+// 2^(e + L) for an integer-valued e and a log2 feature L, as 2^frac(L)
+// scaled by the exact power 2^(e + floor(L)): a float32 sum e + L would
+// round away low bits of L once e is large.  The power is clamped to keep
+// it finite (terms whose exponent leaves that range are zero in float64 or
+// far outside the values the iteration holds).
+__device__ __forceinline__ double pow2_scaled(float L, float e) {
+  const float Li = floorf(L);            // L = Li + Lf exactly, Lf in [0, 1)
+  const float ei = e + Li;               // exact integer sum
+  return ldexp((double)xexp2(L - Li), (int)fminf(fmaxf(ei, -2000.f), 2000.f));
+}
+
+template <class Dom>
+__device__ __forceinline__ void dual_rows_pass(const SolveDesc& D, int64_t lo, int64_t hi,
+                                               double* __restrict__ out) {
+  // columns in chunks of kBlock * kCols (each chunk one sweep over the rows,
+  // reading only that chunk of every row), to keep few registers live;
+  // kRows rows per step keep several loads in flight
+  constexpr int kCols = Dom::kR >= 4 * kBlock ? 4 : (Dom::kR + kBlock - 1) / kBlock;
+  constexpr int kRows = 4;
+  const int r = uniform_i32(D.r);
+  const float* P = uniform_ptr(D.Prow);
+  const float* u = uniform_ptr(D.u);
+  const float* z = uniform_ptr(D.z);
+  const int64_t n = uniform_i64(D.n);
+  for (int k0 = 0; k0 < r; k0 += kBlock * kCols) {
+    double acc[kCols];
+    float fr[kCols];
+    bool on[kCols];
+#pragma unroll
+    for (int c = 0; c < kCols; ++c) {
+      acc[c] = 0.0;
+      const int k = k0 + threadIdx.x + c * kBlock;
+      // frame exponent zE_k; a column the float32 z holds as zero (its
+      // mass is below float32 range) is left at zero, as the iteration
+      // treats it
+      fr[c] = (Dom::kVecStride == 2 && k < r) ? z[k] : 0.f;
+      on[c] = k < r && fr[c] > -1.0e29f;
+    }
+    for (int64_t i0 = lo; i0 < hi; i0 += kRows) {
+      float x[kRows][kCols];
+      float ue[kRows];
+      double um[kRows];
+#pragma unroll
+      for (int q = 0; q < kRows; ++q) {
+        const int64_t i = i0 + q < hi ? i0 + q : hi - 1;   // in bounds, weight 0 past hi
+        const float* row = P + i * (int64_t)r;
+#pragma unroll
+        for (int c = 0; c < kCols; ++c) {
+          const int k = k0 + threadIdx.x + c * kBlock;
+          x[q][c] = on[c] ? row[k] : 0.f;
+        }
+        if (Dom::kVecStride == 2) {
+          ue[q] = u[i];
+          um[q] = i0 + q < hi ? (double)u[n + i] : 0.0;
+        } else {
+          ue[q] = 0.f;
+          um[q] = i0 + q < hi ? (double)u[i] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kRows; ++q) {
+#pragma unroll
+        for (int c = 0; c < kCols; ++c) {
+          if (!on[c]) continue;
+          if (Dom::kVecStride == 2)
+            acc[c] = fma(um[q], pow2_scaled(x[q][c], ue[q] - fr[c]), acc[c]);
+          else
+            acc[c] = fma(um[q], (double)x[q][c], acc[c]);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kCols; ++c) {
+      const int k = k0 + threadIdx.x + c * kBlock;
+      if (k < r) cst(out + k, acc[c]);
+    }
+  }
+}
+
+// sum_j v_j (Pcol_j . z64) over rows [lo, hi) of Pcol, with z64 (r doubles)
+// in LDS; returns the workgroup total (every thread).  Each wave takes
+// kRowsB rows at a time and reads them in chunks of 64 * kChunk columns
+// (many loads in flight); lanes keep v_j-weighted partial dot products, so
+// no per-row reduction is needed.
+template <class Dom>
+__device__ __forceinline__ double dual_cols_pass(const SolveDesc& D, int64_t lo, int64_t hi,
+                                                 const float* vfin, const double* zl,
+                                                 Shared& sh) {
+  constexpr int kRowsB = 4;
+  constexpr int kChunk = Dom::kR >= 8 * 64 ? 8 : (Dom::kR + 63) / 64;
+  const int r = uniform_i32(D.r);
+  const float* P = uniform_ptr(D.Pcol);
+  const float* z = uniform_ptr(D.z);
+  const int64_t m = uniform_i64(D.m);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  double tot = 0.0;
+  for (int64_t j0 = lo + (int64_t)wave * kRowsB; j0 < hi; j0 += (int64_t)kWaves * kRowsB) {
+    double t[kRowsB];
+    float ve[kRowsB];
+    double vm[kRowsB];
+    const float* rowp[kRowsB];
+#pragma unroll
+    for (int q = 0; q < kRowsB; ++q) {
+      const bool ok = j0 + q < hi;
+      const int64_t j = ok ? j0 + q : hi - 1;     // in bounds, weight 0 past hi
+      rowp[q] = P + j * (int64_t)r;
+      t[q] = 0.0;
+      if (Dom::kVecStride == 2) {
+        ve[q] = vfin[j];
+        vm[q] = ok ? (double)vfin[m + j] : 0.0;
+      } else {
+        ve[q] = 0.f;
+        vm[q] = ok ? (double)vfin[j] : 0.0;
+      }
+    }
+    for (int k0 = 0; k0 < r; k0 += 64 * kChunk) {
+      float x[kRowsB][kChunk];
+#pragma unroll
+      for (int q = 0; q < kRowsB; ++q)
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) {
+          const int k = k0 + lane + 64 * c;
+          x[q][c] = k < r ? rowp[q][k] : 0.f;
+        }
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c) {
+        const int k = k0 + lane + 64 * c;
+        if (k >= r) continue;
+        const double zk = zl[k];
+        if (Dom::kVecStride == 2) {
+          const float ze = z[k];
+          if (!(ze > -1.0e29f)) continue;        // a zero column of z
+#pragma unroll
+          for (int q = 0; q < kRowsB; ++q)
+            t[q] = fma(pow2_scaled(x[q][c], ve[q] + ze), zk, t[q]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < kRowsB; ++q) t[q] = fma((double)x[q][c], zk, t[q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kRowsB; ++q) tot = fma(t[q], vm[q], tot);
+  }
+  return block_dsum(tot, sh.d);
+}
+
 // D is the workgroup's LDS copy of the descriptor: its fields are re-read
 // where they are used (LDS is reloaded after every workgroup barrier), so
 // no more than one half-step's worth of them occupy scalar registers.
-template <class Dom>
+template <class Dom, bool ROBUST>
 __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl* ctl,
                           uint64_t tlimit, float* lds, Shared& sh) {
   const int g = uniform_i32(D.g);
@@ -1047,12 +1277,24 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
   auto vbuf = [&](int k) -> float* { return uniform_ptr((k & 1) ? D.v : D.v2); };
   auto wbuf = [&](int k) -> float* { return uniform_ptr((k & 1) ? D.w : D.w2); };
 
+  // the robust kernel only resumes solves the fast kernel left for it
+  if (ROBUST) {
+    const int st = cld(&D.info->status);
+    if (st != kResumeV && st != kResumeU) return;   // the whole gang leaves
+  }
   typename Dom::State S;
   double err = 0.0;
   int bad = 0;
   bool ok = true;
+  int uflow = 0;
+  int status = SK_OK;
+  int kf = 0;
+  double err_final = INFINITY;
+  const bool fixed = D.fixed_iter > 0;
+  const int limit = uniform_i32(fixed ? D.fixed_iter : D.max_iter);
   if (threadIdx.x == 0) cst(D.members + br, (int32_t)blockIdx.x);
 
+  if (!ROBUST) {
   // Weight check: every workgroup sums its own rows of a and columns of b
   // in float64 and counts entries that are not positive and finite; the
   // partials are published with the first half-step's (whose barrier makes
@@ -1083,19 +1325,14 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
 
   // z^(0) = Prow^T u^(0), u^(0) = 1 or the caller's start.
   Dom::template zero<false>(S);
-  Dom::template half_step<MODE_ACCUM>(uniform_ptr(D.Prow), rlo(), rhi(), r,
-                                      uniform_i64(D.n), S, nullptr,
-                                      D.warm ? uniform_ptr(D.u) : nullptr,
-                                      nullptr, err, bad, lds);
+  Dom::template half_step<MODE_ACCUM, false>(uniform_ptr(D.Prow), rlo(), rhi(), r,
+                                             uniform_i64(D.n), S, nullptr,
+                                             D.warm ? uniform_ptr(D.u) : nullptr,
+                                             nullptr, err, bad, lds);
   err = 0.0;
   ok = finish_half_step<Dom, false>(D, br, B, S, uniform_ptr(D.z), true, nullptr, err,
-                                    bad, lds, sh);
+                                    bad, uflow, lds, sh);
 
-  int status = SK_OK;
-  int kf = 0;
-  double err_final = INFINITY;
-  const bool fixed = D.fixed_iter > 0;
-  const int limit = uniform_i32(fixed ? D.fixed_iter : D.max_iter);
   if (ok && bad) status = SK_ERANGE;
   if (ok) {
     if (g > 1) {
@@ -1107,57 +1344,93 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
         !(fabs(wsum_b - 1.0) <= kWeightSumTol))
       status = SK_EINVAL;
   }
+  }  // !ROBUST
 
-  for (int k = 1; ok && status == SK_OK; ++k) {
+  // Update passes accumulate the new r-vector in the frame of the input
+  // one (one exp2 per element serves both sides).  A column whose framed
+  // sum falls below kFrameFloor may have lost terms to float32 underflow
+  // (an anchor far from every point of one cloud at small eps).  The fast
+  // kernel then stops the solve before using that sum and records where
+  // (kResumeV / kResumeU, iteration); the robust kernel launched after it
+  // resumes exactly there and accumulates every later pass with per-column
+  // exponents (the state before the pass is untouched by it, except the
+  // scalings it wrote, which the redo writes again identically).
+  constexpr bool XR = Dom::kVecStride == 2;
+  bool skip_v = false;
+  int k0 = 1;
+  if (ROBUST) {
+    const int st = cld(&D.info->status);
+    k0 = cld(&D.info->iters);
+    skip_v = st == kResumeU;
+    kf = k0 - 1;
+  }
+  auto resume_exit = [&](int code, int k) __attribute__((always_inline)) {
+    if (br == 0 && threadIdx.x == 0) {
+      D.info->status = code;
+      D.info->iters = k;
+    }
+  };
+
+  for (int k = k0; ok && status == SK_OK; ++k) {
     const bool last = k > limit;
-    Dom::load_vec(uniform_ptr(D.z), r, S, lds);
-    Dom::template zero<true>(S);
-    err = 0.0;
-    bad = 0;
-    if (last) {
-      Dom::template half_step<MODE_CHECK>(uniform_ptr(D.Pcol), clo(), chi(), r,
-                                          uniform_i64(D.m), S, uniform_ptr(D.b),
-                                          vbuf(k - 1), nullptr, err, bad,
-                                          lds);
-    } else if (k >= 2) {
-      Dom::template half_step<MODE_UPDATE_CHECK>(uniform_ptr(D.Pcol), clo(), chi(),
-                                                 r, uniform_i64(D.m), S,
-                                                 uniform_ptr(D.b), vbuf(k - 1),
-                                                 vbuf(k), err, bad, lds);
-    } else {
-      Dom::template half_step<MODE_UPDATE>(uniform_ptr(D.Pcol), clo(), chi(), r,
-                                           uniform_i64(D.m), S, uniform_ptr(D.b),
-                                           nullptr, vbuf(k), err, bad, lds);
+    if (!skip_v) {
+      Dom::load_vec(uniform_ptr(D.z), r, S, lds);
+      Dom::template zero<!ROBUST>(S);
+      err = 0.0;
+      bad = 0;
+      if (last) {
+        Dom::template half_step<MODE_CHECK, ROBUST>(uniform_ptr(D.Pcol), clo(), chi(), r,
+                                                    uniform_i64(D.m), S, uniform_ptr(D.b),
+                                                    vbuf(k - 1), nullptr, err, bad, lds);
+      } else if (k >= 2) {
+        Dom::template half_step<MODE_UPDATE_CHECK, ROBUST>(uniform_ptr(D.Pcol), clo(), chi(),
+                                                           r, uniform_i64(D.m), S,
+                                                           uniform_ptr(D.b), vbuf(k - 1),
+                                                           vbuf(k), err, bad, lds);
+      } else {
+        Dom::template half_step<MODE_UPDATE, ROBUST>(uniform_ptr(D.Pcol), clo(), chi(), r,
+                                                     uniform_i64(D.m), S, uniform_ptr(D.b),
+                                                     nullptr, vbuf(k), err, bad, lds);
+      }
+      ok = finish_half_step<Dom, !ROBUST>(D, br, B, S, wbuf(k), !last, uniform_ptr(D.z), err,
+                                          bad, uflow, lds, sh);
+      if (!ok) break;
+      if (XR && !ROBUST && uflow) {
+        resume_exit(kResumeV, k);
+        return;
+      }
+      if (k >= 2) err_final = err;  // error of iteration k-1
+      if (bad) {
+        status = SK_ERANGE;
+        kf = k - 1;
+        break;
+      }
+      if (last) {
+        kf = k - 1;
+        status = (fixed || err_final < D.tol) ? SK_OK : SK_ENOTCONV;
+        break;
+      }
+      if (!fixed && k >= 2 && err_final < D.tol) {
+        kf = k - 1;
+        break;
+      }
     }
-    ok = finish_half_step<Dom, true>(D, br, B, S, wbuf(k), !last, uniform_ptr(D.z), err,
-                                     bad, lds, sh);
-    if (!ok) break;
-    if (k >= 2) err_final = err;  // error of iteration k-1
-    if (bad) {
-      status = SK_ERANGE;
-      kf = k - 1;
-      break;
-    }
-    if (last) {
-      kf = k - 1;
-      status = (fixed || err_final < D.tol) ? SK_OK : SK_ENOTCONV;
-      break;
-    }
-    if (!fixed && k >= 2 && err_final < D.tol) {
-      kf = k - 1;
-      break;
-    }
+    skip_v = false;
     // u-half-step with w^(k).
     Dom::load_vec(wbuf(k), r, S, lds);
-    Dom::template zero<true>(S);
+    Dom::template zero<!ROBUST>(S);
     err = 0.0;
     bad = 0;
-    Dom::template half_step<MODE_UPDATE>(uniform_ptr(D.Prow), rlo(), rhi(), r,
-                                         uniform_i64(D.n), S, uniform_ptr(D.a),
-                                         nullptr, uniform_ptr(D.u), err, bad, lds);
-    ok = finish_half_step<Dom, true>(D, br, B, S, uniform_ptr(D.z), true, wbuf(k), err,
-                                     bad, lds, sh);
+    Dom::template half_step<MODE_UPDATE, ROBUST>(uniform_ptr(D.Prow), rlo(), rhi(), r,
+                                                 uniform_i64(D.n), S, uniform_ptr(D.a),
+                                                 nullptr, uniform_ptr(D.u), err, bad, lds);
+    ok = finish_half_step<Dom, !ROBUST>(D, br, B, S, uniform_ptr(D.z), true, wbuf(k), err,
+                                        bad, uflow, lds, sh);
     if (!ok) break;
+    if (XR && !ROBUST && uflow) {
+      resume_exit(kResumeU, k);
+      return;
+    }
     if (bad) {
       status = SK_ERANGE;
       kf = k;
@@ -1199,22 +1472,61 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
   }
   const double blk = block_dsum(part, sh.d);
   if (threadIdx.x == 0) cst(D.dpart + 2 * g + br, blk);
+  // u^T K v in float64 (see dual_rows_pass): z64 partials into the slots
+  double* myslot = reinterpret_cast<double*>(uniform_ptr(D.slots) +
+                                             (int64_t)blockIdx.x * uniform_i32(D.slot_stride));
+  if (kf >= 1) dual_rows_pass<Dom>(D, rlo(), rhi(), myslot);
+  if (!group_barrier(B)) {
+    if (br == 0 && threadIdx.x == 0) D.info->status = SK_ETIMEOUT;
+    return;
+  }
+  // column slice of z64 summed over the g partials in seat order (float64)
+  // into the second w buffer (free once the final w is in place)
+  double* z64 = reinterpret_cast<double*>(uniform_ptr(D.w2));
+  if (kf >= 1) {
+    const int per = (r + g - 1) / g;
+    const int c0 = br * per, c1 = min(r, c0 + per);
+    for (int k = c0 + threadIdx.x; k < c1; k += kBlock) {
+      double sacc = 0.0;
+      for (int b2 = 0; b2 < g; ++b2) {
+        const double* ps = reinterpret_cast<const double*>(
+            D.slots + (int64_t)cld(D.members + b2) * D.slot_stride);
+        sacc += cld(ps + k);
+      }
+      cst(z64 + k, sacc);
+    }
+  }
+  if (!group_barrier(B)) {
+    if (br == 0 && threadIdx.x == 0) D.info->status = SK_ETIMEOUT;
+    return;
+  }
+  double ukv_blk = 0.0;
+  if (kf >= 1) {
+    double* zl = reinterpret_cast<double*>(lds);
+    __syncthreads();
+    for (int k = threadIdx.x; k < r; k += kBlock) zl[k] = cld(z64 + k);
+    __syncthreads();
+    ukv_blk = dual_cols_pass<Dom>(D, clo(), chi(), vfin, zl, sh);
+  }
+  if (threadIdx.x == 0) cst(D.dpart + 3 * g + br, ukv_blk);
   if (!group_barrier(B)) {
     if (br == 0 && threadIdx.x == 0) D.info->status = SK_ETIMEOUT;
     return;
   }
   if (br == 0) {
     const double tot = group_dsum(D.dpart + 2 * g, g, sh.d);
+    const double ukv = group_dsum(D.dpart + 3 * g, g, sh.d);
     if (threadIdx.x == 0) {
       D.info->iters = kf;
       D.info->status = status;
       D.info->err = err_final;
-      D.info->w_hat = kf >= 1 ? D.eps * tot : NAN;
+      // the dual objective at (u, v): the estimate minus eps (u^T K v - 1)
+      D.info->w_hat = kf >= 1 ? D.eps * (tot - (ukv - 1.0)) : NAN;
     }
   }
 }
 
-template <class Dom>
+template <class Dom, bool ROBUST>
 __global__ void __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(Dom::kWavesPerEU, 8)))
 solver_kernel(const SolveDesc* __restrict__ descs, int count, int total_seats,
@@ -1253,7 +1565,7 @@ solver_kernel(const SolveDesc* __restrict__ descs, int count, int total_seats,
     }
     __syncthreads();
     const int br = seat - uniform_i32(sD.seat0);
-    run_solve<Dom>(sD, br, ctl, tlimit, lds, sh);
+    run_solve<Dom, ROBUST>(sD, br, ctl, tlimit, lds, sh);
     __syncthreads();
   }
 }
@@ -1279,15 +1591,18 @@ __global__ void upload_kernel(unsigned char* dst, UploadPayload p, int nbytes) {
 // ----------------------------------------------------------- dispatch table
 struct SolverClass {
   int rmax;             // largest r of the class
+  int lanes;            // lanes per feature row (G, both domains)
   const void* fn[2];    // kernel symbols: linear, extended range
   void (*launch[2])(dim3, hipStream_t, const SolveDesc*, int, int, LaunchCtl*,
                     uint64_t);
+  void (*launch_robust)(dim3, hipStream_t, const SolveDesc*, int, int, LaunchCtl*,
+                        uint64_t);     // extended range, per-column exponents
 };
 
-template <class Dom>
+template <class Dom, bool ROBUST = false>
 void launch_cls(dim3 grid, hipStream_t s, const SolveDesc* d, int count,
                 int seats, LaunchCtl* ctl, uint64_t tl) {
-  hipLaunchKernelGGL((solver_kernel<Dom>), grid, dim3(kBlock), 0, s, d, count,
+  hipLaunchKernelGGL((solver_kernel<Dom, ROBUST>), grid, dim3(kBlock), 0, s, d, count,
                      seats, ctl, tl);
 }
 
@@ -1295,11 +1610,12 @@ void launch_cls(dim3 grid, hipStream_t s, const SolveDesc* d, int count,
 // kernel; each kernel's lane layout (G lanes per row, C float4 per lane, so
 // 4 G C >= rmax), batch depth U, r-vector placement VL and occupancy W.
 #define SK_CLASS(RMAX, LG, LC, LU, LV, LW, XG, XC, XU, XV, XW)                        \
-  {RMAX,                                                                            \
-   {reinterpret_cast<const void*>(&solver_kernel<LinearDomain<LG, LC, LU, LV, LW>>), \
-    reinterpret_cast<const void*>(&solver_kernel<XRangeDomain<XG, XC, XU, XV, XW>>)}, \
+  {RMAX, LG,                                                                        \
+   {reinterpret_cast<const void*>(&solver_kernel<LinearDomain<LG, LC, LU, LV, LW>, false>), \
+    reinterpret_cast<const void*>(&solver_kernel<XRangeDomain<XG, XC, XU, XV, XW>, false>)}, \
    {&launch_cls<LinearDomain<LG, LC, LU, LV, LW>>,                                   \
-    &launch_cls<XRangeDomain<XG, XC, XU, XV, XW>>}}
+    &launch_cls<XRangeDomain<XG, XC, XU, XV, XW>>},                                  \
+   &launch_cls<XRangeDomain<XG, XC, XU, XV, XW>, true>}
 
 const SolverClass kClasses[] = {
     SK_CLASS(4, 1, 1, 2, true, 4, 1, 1, 2, true, 4),
@@ -1343,6 +1659,11 @@ uint64_t timeout_ticks() {
 int solver_class_rmax(int r) {
   const SolverClass* cls = class_for(r);
   return cls ? cls->rmax : 0;
+}
+
+int solver_class_lanes(int r) {
+  const SolverClass* cls = class_for(r);
+  return cls ? cls->lanes : 0;
 }
 
 int solver_capacity(int r, int xr) {
@@ -1394,14 +1715,24 @@ hipError_t launch_init_ctl(LaunchCtl* ctl, unsigned* bars, int nbars,
 }
 
 hipError_t launch_solver(const SolveDesc* dev_descs, int count, int r, int xr,
-                         int total_seats, int grid, LaunchCtl* ctl,
+                         int total_seats, int grid, LaunchCtl* ctl, unsigned* bars,
                          hipStream_t s) {
   const SolverClass* cls = class_for(r);
   if (!cls) return hipErrorInvalidValue;
   void* tok = prof_begin(kProfSolver, s);
   cls->launch[xr ? 1 : 0](dim3(grid), s, dev_descs, count, total_seats, ctl,
                           timeout_ticks());
-  const hipError_t e = hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && xr) {
+    // solves that met a framed underflow resume here (the others leave at
+    // once); fresh seats and barrier counters for the second launch
+    e = launch_init_ctl(ctl, bars, count, s);
+    if (e == hipSuccess) {
+      cls->launch_robust(dim3(grid), s, dev_descs, count, total_seats, ctl,
+                         timeout_ticks());
+      e = hipGetLastError();
+    }
+  }
   prof_end(tok, s);
   return e;
 }

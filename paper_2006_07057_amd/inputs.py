@@ -36,7 +36,7 @@ __all__ = [
     "gaussian_anchors", "standard_normal_anchors",
     "uniform_weights", "dirichlet_weights",
     "request_stream", "request_arrays", "pixel_batch_sizes",
-    "max_norm",
+    "max_norm", "max_norm_device", "counter_uniform", "pixels_counter", "pixel_batch",
 ]
 
 
@@ -106,6 +106,97 @@ def pixels(seed: int = 0, n: int = 4096, m: int = 4096, d: int = 784) -> Cloud:
     X = rng.uniform(0.0, 1.0, size=(n, d))
     Y = rng.uniform(0.0, 1.0, size=(m, d))
     return Cloud(_f32(X), _f32(Y), uniform_weights(n), uniform_weights(m))
+
+
+# ---------------------------------------------- counter-based pixel points
+# Points of the mixed pixel batch (0.3 TB in all) are made where they are
+# used: on the device for the GPU path, on the host for the oracle, from the
+# same integer counter hash, so both sides get bit-identical arrays without
+# moving them.  The hash is the 32-bit finaliser of MurmurHash3 (Appleby,
+# public domain), applied twice; every product is kept below 2^48 so that
+# int64 arithmetic (numpy or torch, host or device) is exact.
+_M32 = 0xFFFFFFFF
+
+
+def _mul32(h, c: int):
+    """(h * c) mod 2^32 for 0 <= h < 2^32, through two 16-bit halves of c."""
+    lo, hi = c & 0xFFFF, c >> 16
+    return ((h * lo) + (((h * hi) & 0xFFFF) << 16)) & _M32
+
+
+def _fmix32(h):
+    h = h ^ (h >> 16)
+    h = _mul32(h, 0x85EBCA6B)
+    h = h ^ (h >> 13)
+    h = _mul32(h, 0xC2B2AE35)
+    return h ^ (h >> 16)
+
+
+def _salt(key: int, cloud: int) -> int:
+    import numpy as _np
+    return int(_fmix32(_np.int64((2 * key + cloud) & _M32)))
+
+
+def counter_uniform(key: int, cloud: int, rows: int, d: int, device=None,
+                    block: int = 1 << 16):
+    """rows x d float32 values in [0, 1): entry (i, j) is
+    (h >> 8) 2^-24 with h = fmix32(fmix32((i d + j) xor s) + s mod 2^32) and
+    s a salt of (key, cloud).  device None: a numpy array; else a torch
+    tensor made on that device (blocks of `block` rows)."""
+    if rows * d >= 1 << 32:
+        raise ValueError("counter range exceeds 32 bits")
+    s = _salt(key, cloud)
+    if device is None:
+        out = np.empty((rows, d), dtype=np.float32)
+        for i0 in range(0, rows, block):
+            i1 = min(rows, i0 + block)
+            c = np.arange(i0 * d, i1 * d, dtype=np.int64)
+            h = _fmix32((_fmix32(c ^ s) + s) & _M32)
+            out[i0:i1] = ((h >> 8).astype(np.float32) * np.float32(2.0 ** -24)).reshape(i1 - i0, d)
+        return out
+    import torch
+    out = torch.empty((rows, d), dtype=torch.float32, device=device)
+    for i0 in range(0, rows, block):
+        i1 = min(rows, i0 + block)
+        c = torch.arange(i0 * d, i1 * d, dtype=torch.int64, device=device)
+        h = _fmix32((_fmix32(c ^ s) + s) & _M32)
+        out[i0:i1] = ((h >> 8).to(torch.float32) * (2.0 ** -24)).view(i1 - i0, d)
+    return out
+
+
+def pixels_counter(key: int, n: int, m: int, d: int = 784, device=None):
+    """Pixel-like clouds X (n x d), Y (m x d) with entries in [0, 1) from
+    counter_uniform (bit-identical on host and device) and uniform float32
+    weights.  device None: numpy arrays; else torch tensors on it."""
+    X = counter_uniform(key, 0, n, d, device)
+    Y = counter_uniform(key, 1, m, d, device)
+    if device is None:
+        return Cloud(X, Y, uniform_weights(n), uniform_weights(m))
+    import torch
+    a = torch.full((n,), 1.0 / n, dtype=torch.float32, device=device)
+    b = torch.full((m,), 1.0 / m, dtype=torch.float32, device=device)
+    return Cloud(X, Y, a, b)
+
+
+def pixel_batch(seed: int = 0, count: int = 256, lo: int = 2 ** 12, hi: int = 2 ** 20,
+                r_menu=(512, 4096)):
+    """The mixed pixel batch: per problem (index, n, m, r, key) with n, m
+    log-uniform in [lo, hi], r uniform over r_menu (pixel_batch_sizes) and
+    `key` seeding its points (pixels_counter) and anchor draws
+    (standard_normal_anchors)."""
+    sizes = pixel_batch_sizes(seed=seed, count=count, lo=lo, hi=hi, r_menu=r_menu)
+    return [(i, n, m, r, 1000 + 1000 * seed + i) for i, (n, m, r) in enumerate(sizes)]
+
+
+def max_norm_device(*tensors, rows: int = 1 << 16) -> float:
+    """Largest Euclidean row norm over device point arrays, in float64
+    (blocks of `rows` rows)."""
+    best = 0.0
+    for T in tensors:
+        for i in range(0, T.shape[0], rows):
+            blk = T[i:i + rows].double()
+            best = max(best, float((blk * blk).sum(1).max().sqrt().item()))
+    return best
 
 
 def standard_normal_anchors(seed: int, r: int, d: int) -> np.ndarray:

@@ -9,6 +9,7 @@ oracle values, each stamped with the recipe that reproduces it:
 
     python tests/golden/make_golden.py             # the quick fixtures
     python tests/golden/make_golden.py gmm3d_1m    # the 10^6-point mixture
+    python tests/golden/make_golden.py pixel_batch256   # the mixed pixel batch
 """
 import json
 import os
@@ -137,10 +138,57 @@ def gmm3d_1m():
     return out
 
 
-# fixtures regenerated by default; the 10^6-point one only when named
+PIXEL_SAMPLE = (248, 146, 59, 199, 13, 108)
+PIXEL_ROWS = 64          # rows drawn per problem; every PIXEL_KEEP-th is stored
+PIXEL_KEEP = 8
+
+
+def pixel_batch256():
+    """Problems of the mixed pixel batch (inputs.pixel_batch(0): 256
+    problems, n, m log-uniform in [2^12, 2^20], d = 784, r in {512, 4096},
+    eps = 10) with n, m <= 2^17, through the float64 oracle: the three
+    smallest r = 512 problems, the largest r = 512 problem under 2^17
+    points per side, and the two smallest r = 4096 problems.  Points from
+    inputs.pixels_counter (the generator the GPU path runs on the device),
+    the oracle's own Lambert q and anchors from the problem's normal
+    draws; Algorithm 1 to tol = 1e-6 (cap 2000); W_bar, the three terms,
+    iteration counts, and the gradient with respect to X on every eighth of
+    64 rows drawn by default_rng(index) plus its Frobenius norm.  About half
+    an hour on 8 cores."""
+    import time
+    eps, d = 10.0, 784
+    spec = {i: (n, m, r, key) for (i, n, m, r, key) in inputs.pixel_batch(0)}
+    out = {"recipe": "inputs.pixel_batch(0); inputs.pixels_counter(key, n, m, 784); "
+                     "q = oracle.lambert_q(inputs.max_norm(X, Y), 10, 784); "
+                     "U = inputs.gaussian_anchors(key, r, 784, oracle.sigma2_from_q(q, 10)); "
+                     "oracle.divergence_grad_scaled(..., tol=1e-6, max_iter=2000); "
+                     "rows = sorted(default_rng(index).choice(n, 64, replace=False))[::8]",
+           "eps": eps, "problems": {}}
+    for i in PIXEL_SAMPLE:
+        n, m, r, key = spec[i]
+        t0 = time.time()
+        c = inputs.pixels_counter(key, n, m, d)
+        q = oracle.lambert_q(inputs.max_norm(c.X, c.Y), eps, d)
+        U = inputs.gaussian_anchors(key, r, d, oracle.sigma2_from_q(q, eps))
+        dX, _, _, _, div = oracle.divergence_grad_scaled(c.X, c.Y, c.a, c.b, U, eps, q,
+                                                         tol=1e-6, max_iter=2000)
+        rows = sorted(int(x) for x in np.random.default_rng(i).choice(n, PIXEL_ROWS,
+                                                                        replace=False))
+        rows = rows[::PIXEL_KEEP]
+        rec = _div_record(div)
+        rec.update({"n": n, "m": m, "r": r, "key": key, "q": q, "rows": rows,
+                    "grad_x_rows": dX[rows].tolist(),
+                    "grad_x_norm": float(np.linalg.norm(dX))})
+        out["problems"][str(i)] = rec
+        print(f"pixel problem {i} ({n}, {m}, {r}) in {time.time() - t0:.0f} s: "
+              f"W_bar {div.value:.8g} iters {rec['iters']}", flush=True)
+    return out
+
+
+# fixtures regenerated by default; the long ones only when named
 FIXTURES = {"gauss2d_1k": gauss2d_1k, "lambert_q": lambert_q,
             "accelerated_small": accelerated_small}
-LONG_FIXTURES = {"gmm3d_1m": gmm3d_1m}
+LONG_FIXTURES = {"gmm3d_1m": gmm3d_1m, "pixel_batch256": pixel_batch256}
 
 
 def main(names=None):
