@@ -104,8 +104,12 @@ typedef struct {
  *             weights outside the simplex (see sinkhorn_solve);
  *   err       ||v o K^T u - b||_1 of the returned pair (float64);
  *   w_hat     dual estimate eps (a^T log u + b^T log v) of Eq.
- *             (dual-estimate) for the kernel the solver was given,
- *             accumulated in float64 from the float32 scalings. */
+ *             (dual-estimate) for the kernel the solver was given, taken
+ *             as eps (a^T log u + b^T log v - (u^T K v - sum(a))): the same
+ *             value where the last u-update is exact (u^T K v = sum(a)),
+ *             stationary in (u, v) like the objective of Eq. (eval-dual),
+ *             so the float32 rounding of the scalings enters it at second
+ *             order; every sum in float64. */
 typedef struct {
   int32_t iters;
   int32_t status;

@@ -1097,18 +1097,24 @@ __device__ __forceinline__ int uniform_i32(int v) {
 }
 
 // ------------------------------------------------ dual objective at the end
-// The dual estimate eps (a^T log u + b^T log v) equals the dual objective of
-// Eq. (eval-dual) only where u^T K v = 1, which an exact u-update makes
-// true.  With float32 scalings it holds to about 1e-7, and that residual
-// enters the estimate at first order, while the objective itself
-//   eps (a^T log u + b^T log v) - eps (u^T K v - 1)
-// is stationary at the optimum, so rounding of the scalings enters it at
-// second order.  Between divergence terms of similar size (two samples of
-// one distribution) the first-order part dominates W_bar.  The final phase
-// therefore evaluates u^T K v = (Prow^T u) . (Pcol^T v) once more, in
-// float64 from the stored features and scalings: z64 = Prow^T u (per
-// column, relative to the frame 2^zE of the float32 z in the extended
-// range), then sum_j v_j (Pcol_j . z64).
+// The dual estimate eps (a^T log u + b^T log v) of Eq. (dual-estimate)
+// equals the dual objective of Eq. (eval-dual) where u^T K v = 1, which an
+// exact u-update makes true for weights that sum to one (u^T K v = sum(a)
+// after it in general).  With float32 scalings that identity holds to about
+// 1e-7, and the residual enters the estimate at first order, while
+//   eps (a^T log u + b^T log v) - eps (u^T K v - sum(a))
+// equals the estimate wherever the identity holds and is stationary at the
+// optimum (its derivatives in log u_i and log v_j are the marginal
+// residuals), so rounding of the scalings enters it at second order.  Using
+// sum(a) rather than 1 keeps it equal to the estimate for weights whose
+// float32 sum is not exactly one (uniform 1/n), where the two would differ
+// by eps (sum(a) - 1).  Between divergence terms of similar size (two
+// samples of one distribution) the first-order part dominates W_bar.  The
+// final phase therefore evaluates u^T K v = (Prow^T u) . (Pcol^T v) once
+// more, in float64 from the stored features and scalings: z64 = Prow^T u
+// (per column, relative to the frame 2^zE of the float32 z in the extended
+// range), then sum_j v_j (Pcol_j . z64); sum(a) is summed in float64 with
+// the estimate.
 
 // z64 partial of one workgroup over its rows [lo, hi) of Prow, written to
 // its slot as r doubles.  Thread t owns columns t, t + kBlock, ...
@@ -1450,7 +1456,7 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
 
   // Final pair: u^(kf) in D.u, v^(kf) in vbuf[kf&1], w^(kf) in wbuf[kf&1].
   const float* vfin = vbuf(kf);
-  double part = 0.0;
+  double part = 0.0, asum = 0.0;
   if (kf >= 1) {
     const bool copy = (kf & 1) == 0;
     const int64_t c0 = clo(), c1 = chi(), r0 = rlo(), r1 = rhi();
@@ -1467,11 +1473,17 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
     for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
       double lu = Dom::log_scaling(D.u, i, D.n);
       if (D.srow) lu -= (double)D.srow[i];
-      part += (double)D.a[i] * lu;
+      const double ai = (double)D.a[i];
+      part += ai * lu;
+      asum += ai;
     }
   }
   const double blk = block_dsum(part, sh.d);
-  if (threadIdx.x == 0) cst(D.dpart + 2 * g + br, blk);
+  const double ablk = block_dsum(asum, sh.d);
+  if (threadIdx.x == 0) {
+    cst(D.dpart + 2 * g + br, blk);
+    cst(D.dpart + 4 * g + br, ablk);
+  }
   // u^T K v in float64 (see dual_rows_pass): z64 partials into the slots
   double* myslot = reinterpret_cast<double*>(uniform_ptr(D.slots) +
                                              (int64_t)blockIdx.x * uniform_i32(D.slot_stride));
@@ -1516,12 +1528,15 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
   if (br == 0) {
     const double tot = group_dsum(D.dpart + 2 * g, g, sh.d);
     const double ukv = group_dsum(D.dpart + 3 * g, g, sh.d);
+    const double wa = group_dsum(D.dpart + 4 * g, g, sh.d);
     if (threadIdx.x == 0) {
       D.info->iters = kf;
       D.info->status = status;
       D.info->err = err_final;
-      // the dual objective at (u, v): the estimate minus eps (u^T K v - 1)
-      D.info->w_hat = kf >= 1 ? D.eps * (tot - (ukv - 1.0)) : NAN;
+      // the estimate minus eps (u^T K v - sum(a)): equal to it where an exact
+      // u-update holds (u^T K v = sum(a), which is 1 for weights that sum to
+      // one), stationary at the optimum like the objective of Eq. (eval-dual)
+      D.info->w_hat = kf >= 1 ? D.eps * (tot - (ukv - wa)) : NAN;
     }
   }
 }

@@ -1,0 +1,124 @@
+"""The mixed pixel batch at its stated size (256 problems, n, m log-uniform
+in [2^12, 2^20], d = 784, r in {512, 4096}, eps = 10; the mini-batch
+objective of Sec. 4, Eq. final-obj, averages such terms): wave planning and
+the counter generator on the host; on the GPU, the whole batch in HBM-budget
+waves with the problems the float64 oracle can follow (n, m <= 2^17)
+checked against stored oracle values."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2006_07057_amd import inputs
+from parity import check_divergence, check_gradient, float32_wbar_floor
+
+HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _say(*a):
+    print("[gpu-test]", *a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ host
+def test_plan_waves_first_fit_decreasing():
+    from paper_2006_07057_amd import batch
+    foot = [50, 20, 70, 10, 40, 30]
+    waves = batch.plan_waves(foot, 100)
+    # 70 + 30, 50 + 40 + 10, 20
+    assert waves == [[2, 5], [0, 3, 4], [1]]
+    with pytest.raises(ValueError):
+        batch.plan_waves([101], 100)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_plan_waves_places_everything_within_budget(seed):
+    from paper_2006_07057_amd import batch
+    rng = np.random.default_rng(seed)
+    foot = [int(x) for x in rng.integers(1, 100, size=200)]
+    waves = batch.plan_waves(foot, 150)
+    assert sorted(i for w in waves for i in w) == list(range(200))
+    assert all(sum(foot[i] for i in w) <= 150 for w in waves)
+    # first-fit decreasing uses at most 11/9 OPT + 1 waves (Dosa, 2007)
+    assert len(waves) <= 11 / 9 * (sum(foot) / 150) + 2
+
+
+def test_counter_generator_host_equals_torch():
+    """The pixel points are bit-identical whether made by numpy or by torch
+    (the same integer hash), and look like U[0, 1): mean 1/2, variance
+    1/12, no correlation between neighbouring coordinates."""
+    import torch
+    c = inputs.pixels_counter(11, 3000, 2000, 784)
+    t = inputs.pixels_counter(11, 3000, 2000, 784, device="cpu")
+    assert np.array_equal(c.X, t.X.numpy()) and np.array_equal(c.Y, t.Y.numpy())
+    assert c.X.dtype == np.float32 and c.X.min() >= 0.0 and c.X.max() < 1.0
+    assert abs(float(c.X.mean()) - 0.5) < 1e-3
+    assert abs(float(c.X.var()) - 1.0 / 12.0) < 1e-3
+    assert abs(np.corrcoef(c.X[:, :-1].ravel(), c.X[:, 1:].ravel())[0, 1]) < 5e-3
+    assert not np.array_equal(c.X[:100], inputs.counter_uniform(12, 0, 100, 784))
+
+
+def test_batch_footprint_covers_the_state():
+    from paper_2006_07057_amd import api, batch
+    n, m, d, r = 5000, 7000, 784, 4096
+    L = api.state_layout(n, m, r)
+    f = batch.footprint_bytes(n, m, d, r)
+    assert f >= L.total + 4 * (n + m) * d + 4 * n * d
+
+
+# ------------------------------------------------------------------ GPU
+@pytest.mark.gpu
+def test_pixel_batch256_in_waves_matches_oracle():
+    """All 256 problems run (several waves within 70% of free HBM); every
+    solve converges; the six sampled problems with n, m <= 2^17 match the
+    stored float64 oracle values: W_bar and the three estimates within
+    1e-5 (W_bar with the float32 floor where it is nearly zero), the
+    gradient with respect to X on 8 sampled rows within 1e-4 and its norm within
+    1e-4, iteration counts within one."""
+    import torch
+    from paper_2006_07057_amd import api, batch
+    with open(os.path.join(HERE, "pixel_batch256.json")) as f:
+        gold = json.load(f)
+    spec = inputs.pixel_batch(0)
+    keys = {i: key for (i, _, _, _, key) in spec}
+    probs = [batch.BatchProblem(i, n, m, 784, r) for (i, n, m, r, _) in spec]
+
+    def make(p):
+        c = inputs.pixels_counter(keys[p.index], p.n, p.m, p.d, device="cuda:0")
+        U, q = api.gaussian_anchors(inputs.standard_normal_anchors(keys[p.index], p.r, p.d),
+                                    10.0, R=inputs.max_norm_device(c.X, c.Y))
+        return c.X, c.Y, c.a, c.b, torch.from_numpy(U).cuda(), 10.0, q
+
+    seen = {}
+
+    def on_wave(res):
+        _say(f"wave {res.wave}: {len(res.indices)} problems, {res.ms:.0f} ms")
+        outs = res.out.cpu().numpy()
+        for k, i in enumerate(res.indices):
+            inf = res.states[k].infos()
+            assert list(inf["status"]) == [0, 0, 0], (i, inf)
+            assert np.isfinite(outs[k]).all(), i
+            if str(i) in gold["problems"]:
+                g = gold["problems"][str(i)]
+                rows = torch.tensor(g["rows"], device="cuda")
+                seen[i] = (outs[k], [int(x) for x in inf["iters"]],
+                           res.grads[k][rows].double().cpu().numpy(),
+                           float(res.grads[k].double().norm().item()))
+
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    waves = batch.run_waves(probs, make, int(0.7 * free), on_wave=on_wave)
+    _say("waves", len(waves))
+    assert len(waves) >= 2
+    assert sorted(seen) == sorted(int(k) for k in gold["problems"])
+    for i, (out, iters, grow, gnorm) in sorted(seen.items()):
+        g = gold["problems"][str(i)]
+        lab = f"pixel batch256 problem {i} ({g['n']}, {g['m']}, {g['r']})"
+        a = np.full(g["n"], 1.0 / g["n"])
+        b = np.full(g["m"], 1.0 / g["m"])
+        check_divergence(lab, out, (g["W_bar"], g["W_xy"], g["W_xx"], g["W_yy"]),
+                         wbar_floor=float32_wbar_floor(gold["eps"], a, b))
+        assert all(abs(x - y) <= 1 for x, y in zip(iters, g["iters"])), (i, iters, g["iters"])
+        check_gradient(lab + " dX[8 rows]", grow, np.asarray(g["grad_x_rows"]))
+        assert abs(gnorm - g["grad_x_norm"]) <= 1e-4 * g["grad_x_norm"], (i, gnorm)
