@@ -362,13 +362,20 @@ def divergence(X, Y, a, b, U, eps, q, tol=1e-6, max_iter=2000, fixed_iter=0,
 
 def divergence_backward(state: DivergenceState,
                         grad_out: Optional[torch.Tensor] = None,
-                        need=(True, True, True, True)):
-    """Gradients (dX, da, dY, db) of the divergence held in `state`."""
+                        need=(True, True, True, True), out=None):
+    """Gradients (dX, da, dY, db) of the divergence held in `state`.
+    out: optional (dX, da, dY, db) tensors to write (None entries are
+    allocated where `need` asks for them)."""
     dev = state.X.device
-    dX = torch.empty_like(state.X) if need[0] else None
-    da = torch.empty_like(state.a) if need[1] else None
-    dY = torch.empty_like(state.Y) if need[2] else None
-    db = torch.empty_like(state.b) if need[3] else None
+    o = tuple(out) if out is not None else (None, None, None, None)
+    dX = (o[0] if o[0] is not None else torch.empty_like(state.X)) if need[0] else None
+    da = (o[1] if o[1] is not None else torch.empty_like(state.a)) if need[1] else None
+    dY = (o[2] if o[2] is not None else torch.empty_like(state.Y)) if need[2] else None
+    db = (o[3] if o[3] is not None else torch.empty_like(state.b)) if need[3] else None
+    for t, ref, nm in ((dX, state.X, "dX"), (da, state.a, "da"), (dY, state.Y, "dY"),
+                       (db, state.b, "db")):
+        if t is not None:
+            _need(t, nm, shape=tuple(ref.shape))
     ws = getattr(state, "workspace", None)
     if ws is None or ws.numel() < 32768:
         ws = torch.empty(32768, dtype=torch.uint8, device=dev)
@@ -569,17 +576,41 @@ class BatchedDivergenceGraph:
         return self.out, (self.grads if self.backward else None)
 
 
-def divergence_batched(problems: Sequence[tuple], tol=1e-6, max_iter=2000,
-                       fixed_iter=0, range=EXTENDED,
-                       workspace: Optional[torch.Tensor] = None):
-    """Many divergences in batched launches.  ``problems`` holds tuples
-    (X, Y, a, b, U, eps, q).  Returns (out (count, 4) float64, states)."""
+def batched_states(problems: Sequence[tuple], range=EXTENDED):
+    """Device states of a batch (allocated here, filled by
+    divergence_batched)."""
     states: List[DivergenceState] = []
     for P in problems:
         _check_problem_tensors(*P[:5])
         st = DivergenceState(*P)
         st.range = int(range)
         states.append(st)
+    return states
+
+
+def batched_workspace_bytes(states: Sequence[DivergenceState]) -> int:
+    arr = (sk_problem * len(states))(*[s.problem for s in states])
+    return int(lib().sinkhorn_batched_workspace_size(arr, len(states)))
+
+
+def divergence_batched(problems: Sequence[tuple], tol=1e-6, max_iter=2000,
+                       fixed_iter=0, range=EXTENDED,
+                       workspace: Optional[torch.Tensor] = None,
+                       states: Optional[Sequence[DivergenceState]] = None,
+                       out: Optional[torch.Tensor] = None):
+    """Many divergences in batched launches.  ``problems`` holds tuples
+    (X, Y, a, b, U, eps, q).  Returns (out (count, 4) float64, states).
+    states / out / workspace: optional buffers made beforehand
+    (batched_states, batched_workspace_bytes), so that the call allocates
+    nothing."""
+    if states is None:
+        states = batched_states(problems, range)
+    else:
+        states = list(states)
+        if len(states) != len(problems):
+            raise ValueError("one state per problem")
+        for st in states:
+            st.range = int(range)
     count = len(states)
     dev = states[0].X.device
     arr = (sk_problem * count)(*[s.problem for s in states])
@@ -588,7 +619,10 @@ def divergence_batched(problems: Sequence[tuple], tol=1e-6, max_iter=2000,
         raise ValueError("invalid batch")
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=dev)
-    out = torch.empty((count, 4), dtype=torch.float64, device=dev)
+    if out is None:
+        out = torch.empty((count, 4), dtype=torch.float64, device=dev)
+    else:
+        _need(out, "out", dtype=torch.float64, shape=(count, 4))
     ptrs = (ctypes.c_void_p * count)(*[s.buf.data_ptr() for s in states])
     o = _opts(tol, max_iter, fixed_iter, False, range)
     check(lib().sinkhorn_divergence_batched(arr, count, ctypes.byref(o),

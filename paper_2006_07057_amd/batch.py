@@ -88,7 +88,8 @@ def run_waves(problems: Sequence[BatchProblem], make: Callable, budget: int,
     region).  on_wave(result) receives each wave's results (W_bar and the
     three estimates per problem, states, dX) before its memory is released.
     The compute of a wave (features, solves, reductions, gradients) is timed
-    with events on the launch stream.  Returns the wave plan."""
+    with events on the launch stream; its buffers (states, workspace,
+    outputs) are allocated before the timed region.  Returns the wave plan."""
     dev = torch.device(device)
     foot = [footprint_bytes(p.n, p.m, p.d, p.r, grad_x) for p in problems]
     # the packed launches' partial r-vectors and descriptors are shared by
@@ -97,19 +98,27 @@ def run_waves(problems: Sequence[BatchProblem], make: Callable, budget: int,
     ws = None
     for w, idx in enumerate(waves):
         probs = [make(problems[i]) for i in idx]
+        states = api.batched_states(probs)
+        need = api.batched_workspace_bytes(states)
+        if ws is None or ws.numel() < need:
+            ws = None
+            ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        out = torch.empty((len(idx), 4), dtype=torch.float64, device=dev)
+        gbuf = [torch.empty_like(st.X) if grad_x else None for st in states]
         stream = torch.cuda.current_stream(dev)
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         t0.record(stream)
         out, states = api.divergence_batched(probs, tol=tol, max_iter=max_iter,
-                                             fixed_iter=fixed_iter, workspace=ws)
-        ws = states[0].workspace
-        grads = [api.divergence_backward(st, need=(True, False, False, False))[0]
-                 if grad_x else None for st in states]
+                                             fixed_iter=fixed_iter, workspace=ws,
+                                             states=states, out=out)
+        grads = [api.divergence_backward(st, need=(True, False, False, False),
+                                         out=(gb, None, None, None))[0]
+                 if grad_x else None for st, gb in zip(states, gbuf)]
         t1.record(stream)
         t1.synchronize()
         res = WaveResult(w, list(idx), out, states, grads, t0.elapsed_time(t1))
         if on_wave is not None:
             on_wave(res)
-        del probs, out, states, grads, res
+        del probs, out, states, grads, gbuf, res
     return waves

@@ -48,7 +48,7 @@ struct SolveDesc {
 };
 
 // float64 partials per workgroup seat of a solve (SolveDesc::dpart).
-constexpr int kDpartSlots = 6;
+constexpr int kDpartSlots = 7;
 
 // Launch-wide control block (zeroed by init_ctl before each launch).
 struct LaunchCtl {

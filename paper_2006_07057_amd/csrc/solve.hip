@@ -54,8 +54,7 @@ constexpr float kNegBig = -1.0e30f;   // "log of zero" sentinel (finite)
 // the simplex); their sum is checked in float64 to this tolerance.
 constexpr double kWeightSumTol = 1e-5;
 // A framed sum below this (relative to its column frame) may have lost
-// terms to float32 underflow: the solve then accumulates with per-column
-// exponents from that half-step on (see run_solve).
+// terms to float32 underflow ("lossy" column, see run_solve).
 constexpr float kFrameFloor = 7.8886091e-31f;   // 2^-100
 // Internal solve states left in sk_solve_info.status by the fast kernel for
 // the robust one (never returned to callers: the robust kernel overwrites
@@ -368,7 +367,10 @@ struct LinearDomain {
                                    State& S, const float* __restrict__ target,
                                    const float* __restrict__ sold,
                                    float* __restrict__ snew, double& err,
-                                   int& bad, const float* lds) {
+                                   int& bad, int& guard, double guard_min,
+                                   const float* lds) {
+    (void)guard;
+    (void)guard_min;
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -699,9 +701,10 @@ struct XRangeDomain {
   __device__ __forceinline__ static void half_step(const float* __restrict__ P, int64_t lo,
                                    int64_t hi, int r, int64_t nrows, State& S,
                                    const float* __restrict__ target,
-                                   const float* __restrict__ sold,
-                                   float* __restrict__ snew, double& err,
-                                   int& bad, const float* lds) {
+                                   const float* sold, float* snew, double& err,
+                                   int& bad, int& guard, double guard_min,
+                                   const float* lds) {
+    // sold and snew are the same array in a guarded u-pass (no restrict)
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -711,6 +714,8 @@ struct XRangeDomain {
     const int nrel = (int)(hi - lo);
 
     bool started = false;
+    // smallest current marginal of the rows checked (lossy-column guard)
+    double cmin = INFINITY;
     // Loads are unconditional: rows past `hi` read row hi-1, masked columns
     // read column 0; both are neutralised afterwards (zero weight, or the
     // zero r-vector entry).  Addresses: wave-uniform batch base plus a small
@@ -758,6 +763,12 @@ struct XRangeDomain {
         const int64_t row = base + rr;
         const bool rv = rr < rem;
         if (MODE == MODE_ACCUM) {
+          // snew: record the implicit start 1 = (0, 1) (for a later guarded
+          // u-pass, which reads the old u)
+          if (snew && rv && cl == 0) {
+            gst(snew + row, 0.0f);
+            gst(snew + nrows + row, 1.0f);
+          }
           accum_row(S, B.x[uu], rv ? B.toE[uu] : kNegBig, rv ? B.toM[uu] : 0.f,
                     rv, started);
           continue;
@@ -793,8 +804,10 @@ struct XRangeDomain {
           if (rv && cl == 0) {
             const double prod = (double)B.toM[uu] * (double)ssum;
             const double ex = (double)B.toE[uu] + (double)mx;
-            err += fabs(ldexp(prod, (int)fmax(fmin(ex, 2000.0), -2000.0)) -
-                        (double)B.tw[uu]);
+            // the row's current marginal: old scaling x sum
+            const double cj = ldexp(prod, (int)fmax(fmin(ex, 2000.0), -2000.0));
+            err += fabs(cj - (double)B.tw[uu]);
+            cmin = fmin(cmin, cj);
           }
         }
         if (MODE != MODE_CHECK) {
@@ -842,6 +855,9 @@ struct XRangeDomain {
       process(Bb, rel);
       if (nr >= nrel) break;
       rel = nr;
+    }
+    if (MODE == MODE_UPDATE_CHECK || MODE == MODE_CHECK) {
+      if (!(cmin >= guard_min)) guard = 1;
     }
   }
 
@@ -1033,18 +1049,29 @@ struct Shared {
 // workgroup partials + barrier + column slice), publish (err, bad) and
 // return the group totals through err/bad.  Returns false if aborted.
 // FRAMED: update pass whose accumulators are relative to the input r-vector
-// `frame` (extended range); otherwise the first pass.
+// `frame` (extended range); otherwise the first pass.  uflow returns whether
+// the new r-vector has lossy columns.  With guard_on (the input r-vector had
+// lossy columns), guard carries in this workgroup's rows that failed the
+// marginal test and returns the group's verdict; on failure nothing is
+// written to dst (the input of the pass that made the lossy vector stays
+// intact for the robust kernel) and the group leaves together.
 template <class Dom, bool FRAMED>
 __device__ __forceinline__ bool finish_half_step(
     const SolveDesc& D, int br, BarrierState& B, typename Dom::State& S,
     float* __restrict__ dst, bool reduce_vec, const float* frame, double& err,
-    int& bad, int& uflow, float* lds, Shared& sh) {
+    int& bad, int& uflow, bool guard_on, int& guard, float* lds, Shared& sh) {
   __shared__ int s_uflow;
   const int g = D.g;
   const double e_blk = block_dsum(err, sh.d);
   const double b_blk = block_dsum((double)bad, sh.d);
+  const double g_blk = guard_on ? block_dsum((double)guard, sh.d) : 0.0;
+  guard = 0;
   if (threadIdx.x == 0) s_uflow = 0;
   __syncthreads();
+  if (guard_on && g == 1 && g_blk > 0.0) {
+    guard = 1;
+    return true;
+  }
   if (reduce_vec) {
     if (g == 1) {
       Dom::template block_store<FRAMED>(S, dst, D.r, lds, frame, true, &s_uflow);
@@ -1057,9 +1084,14 @@ __device__ __forceinline__ bool finish_half_step(
   if (threadIdx.x == 0) {
     cst(D.dpart + br, e_blk);
     cst(D.dpart + g + br, b_blk);
+    if (guard_on) cst(D.dpart + 6 * g + br, g_blk);
   }
   if (!group_barrier(B)) return false;
   if (g > 1) {
+    if (guard_on && group_dsum(D.dpart + 6 * g, g, sh.d) > 0.0) {
+      guard = 1;
+      return true;
+    }
     if (reduce_vec)
       Dom::template column_reduce<FRAMED>(D.slots, D.slot_stride, D.members, g, D.r,
                                           br, dst, lds, frame, &s_uflow);
@@ -1293,7 +1325,15 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
   int bad = 0;
   bool ok = true;
   int uflow = 0;
+  int guard = 0;
   int status = SK_OK;
+  // the smallest current marginal a row may have while the r-vector it is
+  // summed against has lossy columns (derivation in the loop below):
+  // r 2^25 (2^-100 + max(n, m) 2^-126)
+  const double guard_min = [&]() {
+    const int64_t nm = D.n > D.m ? D.n : D.m;
+    return (double)D.r * 0x1p25 * (0x1p-100 + (double)nm * 0x1p-126);
+  }();
   int kf = 0;
   double err_final = INFINITY;
   const bool fixed = D.fixed_iter > 0;
@@ -1334,10 +1374,11 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
   Dom::template half_step<MODE_ACCUM, false>(uniform_ptr(D.Prow), rlo(), rhi(), r,
                                              uniform_i64(D.n), S, nullptr,
                                              D.warm ? uniform_ptr(D.u) : nullptr,
-                                             nullptr, err, bad, lds);
+                                             D.warm ? nullptr : uniform_ptr(D.u), err, bad,
+                                             guard, guard_min, lds);
   err = 0.0;
   ok = finish_half_step<Dom, false>(D, br, B, S, uniform_ptr(D.z), true, nullptr, err,
-                                    bad, uflow, lds, sh);
+                                    bad, uflow, false, guard, lds, sh);
 
   if (ok && bad) status = SK_ERANGE;
   if (ok) {
@@ -1354,15 +1395,32 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
 
   // Update passes accumulate the new r-vector in the frame of the input
   // one (one exp2 per element serves both sides).  A column whose framed
-  // sum falls below kFrameFloor may have lost terms to float32 underflow
-  // (an anchor far from every point of one cloud at small eps).  The fast
-  // kernel then stops the solve before using that sum and records where
-  // (kResumeV / kResumeU, iteration); the robust kernel launched after it
-  // resumes exactly there and accumulates every later pass with per-column
-  // exponents (the state before the pass is untouched by it, except the
-  // scalings it wrote, which the redo writes again identically).
+  // sum f_k falls below kFrameFloor = 2^-100 may have lost terms to float32
+  // underflow ("lossy"): an anchor that carries almost no mass, which is
+  // common (r = 4096 Gaussian anchors in d = 784 leave a few below 2^-110
+  // at every iteration) and harmless unless a row of the other side leans
+  // on that anchor, as at small eps when an anchor lies near some points
+  // of one cloud only.  Bound: a pass adds nm e_k per row to column k with
+  // nm <= 4 x its target weight, so what underflow (or a flushed partial
+  // sum) drops is below 2^-126 (sum of weights, or rows per column); the
+  // mass the plan puts through anchor k, f_k zM_k plus that, is below
+  // m_k = 2^-100 + N 2^-126 (N = max(n, m)).  When the next pass sums a
+  // row j against this r-vector, anchor k's share of the row's sum is at
+  // most m_k / c_j, c_j the row's current marginal (its old scaling times
+  // the sum), because the anchor's mass includes that row's part of it.
+  // With at most r lossy columns the dropped share stays below 2^-25 (under
+  // float32 rounding of the sum) when c_j >= r m_k 2^25 (guard_min).  The
+  // consuming pass therefore checks every row against that floor (a u-pass
+  // loads the old u for it); if a row fails, the fast kernel stops before
+  // anything that pass would overwrite is written and records the pass
+  // that made the lossy vector (kResumeV / kResumeU, iteration); the robust
+  // kernel launched after it resumes exactly there and accumulates every
+  // later pass with per-column exponents (the state that pass reads is
+  // untouched, except the scalings it wrote, which the redo writes again
+  // identically).
   constexpr bool XR = Dom::kVecStride == 2;
   bool skip_v = false;
+  bool lossy = false;   // the r-vector the next pass reads has lossy columns
   int k0 = 1;
   if (ROBUST) {
     const int st = cld(&D.info->status);
@@ -1384,27 +1442,34 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
       Dom::template zero<!ROBUST>(S);
       err = 0.0;
       bad = 0;
+      guard = 0;
       if (last) {
         Dom::template half_step<MODE_CHECK, ROBUST>(uniform_ptr(D.Pcol), clo(), chi(), r,
                                                     uniform_i64(D.m), S, uniform_ptr(D.b),
-                                                    vbuf(k - 1), nullptr, err, bad, lds);
+                                                    vbuf(k - 1), nullptr, err, bad, guard,
+                                                    guard_min, lds);
       } else if (k >= 2) {
         Dom::template half_step<MODE_UPDATE_CHECK, ROBUST>(uniform_ptr(D.Pcol), clo(), chi(),
                                                            r, uniform_i64(D.m), S,
                                                            uniform_ptr(D.b), vbuf(k - 1),
-                                                           vbuf(k), err, bad, lds);
+                                                           vbuf(k), err, bad, guard,
+                                                           guard_min, lds);
       } else {
         Dom::template half_step<MODE_UPDATE, ROBUST>(uniform_ptr(D.Pcol), clo(), chi(), r,
                                                      uniform_i64(D.m), S, uniform_ptr(D.b),
-                                                     nullptr, vbuf(k), err, bad, lds);
+                                                     nullptr, vbuf(k), err, bad, guard,
+                                                     guard_min, lds);
       }
+      // z^(k-1) (from the u-pass of iteration k-1) was lossy: guard the rows
+      const bool gv = XR && !ROBUST && lossy;
       ok = finish_half_step<Dom, !ROBUST>(D, br, B, S, wbuf(k), !last, uniform_ptr(D.z), err,
-                                          bad, uflow, lds, sh);
+                                          bad, uflow, gv, guard, lds, sh);
       if (!ok) break;
-      if (XR && !ROBUST && uflow) {
-        resume_exit(kResumeV, k);
+      if (gv && guard) {
+        resume_exit(kResumeU, k - 1);
         return;
       }
+      lossy = XR && !ROBUST && !last && uflow;
       if (k >= 2) err_final = err;  // error of iteration k-1
       if (bad) {
         status = SK_ERANGE;
@@ -1427,16 +1492,32 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
     Dom::template zero<!ROBUST>(S);
     err = 0.0;
     bad = 0;
-    Dom::template half_step<MODE_UPDATE, ROBUST>(uniform_ptr(D.Prow), rlo(), rhi(), r,
-                                                 uniform_i64(D.n), S, uniform_ptr(D.a),
-                                                 nullptr, uniform_ptr(D.u), err, bad, lds);
+    // w^(k) was lossy: guard the rows, reading the old u before it is
+    // overwritten (each row is read before it is written, by the same lanes;
+    // before the first u-update D.u holds the start, which the first pass
+    // records when it is the implicit 1)
+    const bool gu = XR && !ROBUST && lossy;
+    guard = 0;
+    if (gu) {
+      Dom::template half_step<MODE_UPDATE_CHECK, ROBUST>(uniform_ptr(D.Prow), rlo(), rhi(), r,
+                                                         uniform_i64(D.n), S,
+                                                         uniform_ptr(D.a), uniform_ptr(D.u),
+                                                         uniform_ptr(D.u), err, bad, guard,
+                                                         guard_min, lds);
+    } else {
+      Dom::template half_step<MODE_UPDATE, ROBUST>(uniform_ptr(D.Prow), rlo(), rhi(), r,
+                                                   uniform_i64(D.n), S, uniform_ptr(D.a),
+                                                   nullptr, uniform_ptr(D.u), err, bad, guard,
+                                                   guard_min, lds);
+    }
     ok = finish_half_step<Dom, !ROBUST>(D, br, B, S, uniform_ptr(D.z), true, wbuf(k), err,
-                                        bad, uflow, lds, sh);
+                                        bad, uflow, gu, guard, lds, sh);
     if (!ok) break;
-    if (XR && !ROBUST && uflow) {
-      resume_exit(kResumeU, k);
+    if (gu && guard) {
+      resume_exit(kResumeV, k);
       return;
     }
+    lossy = XR && !ROBUST && uflow;
     if (bad) {
       status = SK_ERANGE;
       kf = k;
