@@ -210,14 +210,44 @@ int run_solves(const std::vector<SolveSpec>& specs, const sk_solve_opts* o,
     bool small = true;
     for (int i : order)
       small = small && 4 * (specs[i].n + specs[i].m) * (int64_t)specs[i].r <= kSideBySideBytes;
+    // When the shares rounded up need more seats than the grid holds but the
+    // shares rounded down (at least 1) do not, the seats are apportioned
+    // instead (largest remainders first, Hamilton's method), so that every
+    // gang starts at once: with rounded-up shares the last gang would have
+    // members without a workgroup until a whole other solve finished (three
+    // equal solves: 86 + 86 + 86 seats on 256 workgroups).
     std::vector<int> gshare(specs.size());
     if (order.size() > 3 || (order.size() > 1 && small)) {
       double total = 0.0;
       for (int i : order) total += (double)(specs[i].n + specs[i].m) * specs[i].r;
+      int64_t sum_up = 0, sum_down = 0;
+      std::vector<double> quota(specs.size());
       for (int i : order) {
         const double w = (double)(specs[i].n + specs[i].m) * specs[i].r;
-        const int64_t gi = (int64_t)ceil((double)capdev * w / total);
+        quota[i] = (double)capdev * w / total;
+        const int64_t gi = (int64_t)ceil(quota[i]);
         gshare[i] = (int)std::max<int64_t>(1, std::min<int64_t>(gi, gplan[i]));
+        sum_up += gshare[i];
+        sum_down += std::max<int64_t>(1, std::min<int64_t>((int64_t)floor(quota[i]), gplan[i]));
+      }
+      if (sum_up > capdev && sum_down <= capdev) {
+        int64_t left = capdev;
+        for (int i : order) {
+          gshare[i] = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)floor(quota[i]),
+                                                                    gplan[i]));
+          left -= gshare[i];
+        }
+        std::vector<int> byrem(order);
+        std::stable_sort(byrem.begin(), byrem.end(), [&](int x, int y) {
+          return quota[x] - floor(quota[x]) > quota[y] - floor(quota[y]);
+        });
+        for (int i : byrem) {
+          if (left <= 0) break;
+          if (gshare[i] < gplan[i] && (double)gshare[i] < quota[i]) {
+            ++gshare[i];
+            --left;
+          }
+        }
       }
     } else {
       for (int i : order) gshare[i] = gplan[i];

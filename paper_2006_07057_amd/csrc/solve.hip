@@ -1148,153 +1148,280 @@ __device__ __forceinline__ int uniform_i32(int v) {
 // range), then sum_j v_j (Pcol_j . z64); sum(a) is summed in float64 with
 // the estimate.
 
-// z64 partial of one workgroup over its rows [lo, hi) of Prow, written to
-// its slot as r doubles.  Thread t owns columns t, t + kBlock, ...
 // 2^(e + L) for an integer-valued e and a log2 feature L, as 2^frac(L)
 // scaled by the exact power 2^(e + floor(L)): a float32 sum e + L would
 // round away low bits of L once e is large.  The power is clamped to keep
 // it finite (terms whose exponent leaves that range are zero in float64 or
 // far outside the values the iteration holds).
 __device__ __forceinline__ double pow2_scaled(float L, float e) {
+  L = fmaxf(L, -2000.f);                 // a zero feature (-inf) gives 0
   const float Li = floorf(L);            // L = Li + Lf exactly, Lf in [0, 1)
   const float ei = e + Li;               // exact integer sum
   return ldexp((double)xexp2(L - Li), (int)fminf(fmaxf(ei, -2000.f), 2000.f));
 }
 
+// z64 partial of one workgroup over its rows [lo, hi) of Prow, written to
+// its slot as r doubles.  Thread t owns float4 column groups: t, t + kBlock,
+// ... (kJ of them) when r >= 4 kBlock; for smaller r, column group t % (r/4)
+// of row group t / (r/4), the row groups taking interleaved batches of rows
+// and their partials being added in LDS in row-group order.  Rows come in
+// batches of kRows with the next batch in flight while one is summed (the
+// loads are 16-byte, whole rows per batch), so that enough bytes are in
+// flight at one wave per SIMD.  Every sum runs in a fixed order.
 template <class Dom>
 __device__ __forceinline__ void dual_rows_pass(const SolveDesc& D, int64_t lo, int64_t hi,
-                                               double* __restrict__ out) {
-  // columns in chunks of kBlock * kCols (each chunk one sweep over the rows,
-  // reading only that chunk of every row), to keep few registers live;
-  // kRows rows per step keep several loads in flight
-  constexpr int kCols = Dom::kR >= 4 * kBlock ? 4 : (Dom::kR + kBlock - 1) / kBlock;
-  constexpr int kRows = 4;
+                                               double* __restrict__ out, float* ldsf) {
+  // column groups per thread (kJT) in sweeps of kJ over the rows (a sweep
+  // reads its part of every row); <= 8 float4 per batch, fewer where the
+  // class runs several waves per SIMD
+  constexpr int kJT = (Dom::kR + 4 * kBlock - 1) / (4 * kBlock);
+  constexpr int kJ = kJT == 4 ? 2 : kJT;
+  constexpr int kSweeps = kJT / kJ;
+  constexpr int kRows = kJ == 1 ? (Dom::kWavesPerEU >= 4 ? 2 : 4) : 8 / kJ;
+  constexpr bool XR = Dom::kVecStride == 2;
   const int r = uniform_i32(D.r);
+  const int r4 = r >> 2;
   const float* P = uniform_ptr(D.Prow);
   const float* u = uniform_ptr(D.u);
   const float* z = uniform_ptr(D.z);
   const int64_t n = uniform_i64(D.n);
-  for (int k0 = 0; k0 < r; k0 += kBlock * kCols) {
-    double acc[kCols];
-    float fr[kCols];
-    bool on[kCols];
+  const int t = threadIdx.x;
+  const int groups = kJ == 1 ? max(1, kBlock / r4) : 1;
+  const int h = kJ == 1 ? t / r4 : 0;
+  const bool active = h < groups;
+  for (int sw = 0; sw < kSweeps; ++sw) {
+  int coff[kJ];
+  bool cv[kJ];
+  float fr[kJ][4];
+  bool on[kJ][4];
+  double acc[kJ][4];
 #pragma unroll
-    for (int c = 0; c < kCols; ++c) {
-      acc[c] = 0.0;
-      const int k = k0 + threadIdx.x + c * kBlock;
+  for (int j = 0; j < kJ; ++j) {
+    const int c4 = kJ == 1 ? t % r4 : t + kBlock * (sw * kJ + j);
+    cv[j] = active && c4 < r4;
+    coff[j] = cv[j] ? 4 * c4 : 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
       // frame exponent zE_k; a column the float32 z holds as zero (its
       // mass is below float32 range) is left at zero, as the iteration
       // treats it
-      fr[c] = (Dom::kVecStride == 2 && k < r) ? z[k] : 0.f;
-      on[c] = k < r && fr[c] > -1.0e29f;
-    }
-    for (int64_t i0 = lo; i0 < hi; i0 += kRows) {
-      float x[kRows][kCols];
-      float ue[kRows];
-      double um[kRows];
-#pragma unroll
-      for (int q = 0; q < kRows; ++q) {
-        const int64_t i = i0 + q < hi ? i0 + q : hi - 1;   // in bounds, weight 0 past hi
-        const float* row = P + i * (int64_t)r;
-#pragma unroll
-        for (int c = 0; c < kCols; ++c) {
-          const int k = k0 + threadIdx.x + c * kBlock;
-          x[q][c] = on[c] ? row[k] : 0.f;
-        }
-        if (Dom::kVecStride == 2) {
-          ue[q] = u[i];
-          um[q] = i0 + q < hi ? (double)u[n + i] : 0.0;
-        } else {
-          ue[q] = 0.f;
-          um[q] = i0 + q < hi ? (double)u[i] : 0.0;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kRows; ++q) {
-#pragma unroll
-        for (int c = 0; c < kCols; ++c) {
-          if (!on[c]) continue;
-          if (Dom::kVecStride == 2)
-            acc[c] = fma(um[q], pow2_scaled(x[q][c], ue[q] - fr[c]), acc[c]);
-          else
-            acc[c] = fma(um[q], (double)x[q][c], acc[c]);
-        }
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < kCols; ++c) {
-      const int k = k0 + threadIdx.x + c * kBlock;
-      if (k < r) cst(out + k, acc[c]);
+      fr[j][e] = (XR && cv[j]) ? z[coff[j] + e] : 0.f;
+      on[j][e] = cv[j] && fr[j][e] > -1.0e29f;
+      acc[j][e] = 0.0;
     }
   }
+  struct RowBatch {
+    float4 x[kRows][kJ];
+    float ue[kRows];
+    double um[kRows];
+  };
+  auto load = [&](RowBatch& bt, int64_t i0) {
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) {
+      const bool ok = i0 + q < hi;
+      const int64_t i = ok ? i0 + q : hi - 1;     // in bounds, weight 0 past hi
+      const float* row = P + i * (int64_t)r;
+#pragma unroll
+      for (int j = 0; j < kJ; ++j) bt.x[q][j] = gld4s(row + coff[j]);
+      if (XR) {
+        bt.ue[q] = u[i];
+        bt.um[q] = ok ? (double)u[n + i] : 0.0;
+      } else {
+        bt.ue[q] = 0.f;
+        bt.um[q] = ok ? (double)u[i] : 0.0;
+      }
+    }
+  };
+  // branch-free: a column that is off adds an explicit zero
+  auto sum = [&](const RowBatch& bt) {
+#pragma unroll
+    for (int q = 0; q < kRows; ++q)
+#pragma unroll
+      for (int j = 0; j < kJ; ++j) {
+        const float xv[4] = {bt.x[q][j].x, bt.x[q][j].y, bt.x[q][j].z, bt.x[q][j].w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double tv = XR ? pow2_scaled(xv[e], bt.ue[q] - fr[j][e]) : (double)xv[e];
+          acc[j][e] = fma(bt.um[q], on[j][e] ? tv : 0.0, acc[j][e]);
+        }
+      }
+  };
+  const int64_t stride = (int64_t)groups * kRows;
+  int64_t i0 = lo + (int64_t)h * kRows;
+  if (active && i0 < hi) {
+    RowBatch A, B;
+    load(A, i0);
+    for (;;) {
+      int64_t i1 = i0 + stride;
+      load(B, i1 < hi ? i1 : i0);
+      sum(A);
+      if (i1 >= hi) break;
+      i0 = i1;
+      i1 = i0 + stride;
+      load(A, i1 < hi ? i1 : i0);
+      sum(B);
+      if (i1 >= hi) break;
+      i0 = i1;
+    }
+  }
+  if (kJT == 1) {
+    if (groups > 1) {
+      // add the row groups' partials, two columns at a time (kBlock x 2
+      // doubles of LDS), in row-group order
+      double* L = reinterpret_cast<double*>(ldsf);
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        __syncthreads();
+        L[2 * t] = acc[0][2 * p];
+        L[2 * t + 1] = acc[0][2 * p + 1];
+        __syncthreads();
+        if (h == 0 && cv[0]) {
+          double s0 = 0.0, s1 = 0.0;
+          for (int hh = 0; hh < groups; ++hh) {
+            s0 += L[2 * (hh * r4 + t)];
+            s1 += L[2 * (hh * r4 + t) + 1];
+          }
+          acc[0][2 * p] = s0;
+          acc[0][2 * p + 1] = s1;
+        }
+      }
+      __syncthreads();
+    }
+    if (h == 0 && cv[0]) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cst(out + coff[0] + e, acc[0][e]);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kJ; ++j)
+      if (cv[j]) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cst(out + coff[j] + e, acc[j][e]);
+      }
+  }
+  }  // sweeps
 }
 
 // sum_j v_j (Pcol_j . z64) over rows [lo, hi) of Pcol, with z64 (r doubles)
-// in LDS; returns the workgroup total (every thread).  Each wave takes
-// kRowsB rows at a time and reads them in chunks of 64 * kChunk columns
-// (many loads in flight); lanes keep v_j-weighted partial dot products, so
-// no per-row reduction is needed.
+// and the float32 frame exponents zE (r floats) in LDS; returns the
+// workgroup total (every thread).  Each wave takes rows in turn; a lane
+// owns float4 column groups lane, lane + 64, ... (kC of them), or for
+// r < 256 a lane group of L lanes (a power of two >= r/4) takes one row,
+// 64 / L rows side by side.  Batches of kRowsB rows per lane group, the
+// next in flight while one is summed; lanes keep v_j-weighted partial dot
+// products, so no per-row reduction is needed.
 template <class Dom>
 __device__ __forceinline__ double dual_cols_pass(const SolveDesc& D, int64_t lo, int64_t hi,
                                                  const float* vfin, const double* zl,
-                                                 Shared& sh) {
-  constexpr int kRowsB = 4;
-  constexpr int kChunk = Dom::kR >= 8 * 64 ? 8 : (Dom::kR + 63) / 64;
+                                                 const float* zel, Shared& sh) {
+  // float4 column groups per lane (kCT) in sweeps of kC over the rows
+  constexpr int kCT = (Dom::kR + 255) / 256;
+  constexpr int kSweeps = (kCT + 7) / 8;
+  constexpr int kC = kCT / kSweeps;
+  constexpr int kRowsB = kC == 1 ? (Dom::kWavesPerEU >= 4 ? 2 : 4) : (kC >= 8 ? 1 : 8 / kC);
+  // a second batch in flight while one is summed, where registers allow
+  constexpr bool kPipe = kC * kRowsB <= 8;
+  constexpr bool XR = Dom::kVecStride == 2;
   const int r = uniform_i32(D.r);
+  const int r4 = r >> 2;
   const float* P = uniform_ptr(D.Pcol);
-  const float* z = uniform_ptr(D.z);
   const int64_t m = uniform_i64(D.m);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  int Lw = 64;
+  if (kCT == 1) {
+    Lw = 1;
+    while (Lw < r4) Lw <<= 1;
+  }
+  const int rpw = 64 / Lw;              // rows side by side in a wave
+  const int sub = lane / Lw;
+  const int cl = lane % Lw;
   double tot = 0.0;
-  for (int64_t j0 = lo + (int64_t)wave * kRowsB; j0 < hi; j0 += (int64_t)kWaves * kRowsB) {
-    double t[kRowsB];
+  for (int sw = 0; sw < kSweeps; ++sw) {
+  int coff[kC];
+  bool cv[kC];
+#pragma unroll
+  for (int c = 0; c < kC; ++c) {
+    const int c4 = cl + 64 * (sw * kC + c);
+    cv[c] = c4 < r4;
+    coff[c] = cv[c] ? 4 * c4 : 0;
+  }
+  struct RowBatch {
+    float4 x[kRowsB][kC];
     float ve[kRowsB];
     double vm[kRowsB];
-    const float* rowp[kRowsB];
+  };
+  // rows of this lane group: j = lo + (wave * rpw + sub) * kRowsB + q,
+  // batches stepping by kWaves * rpw * kRowsB
+  const int64_t stride = (int64_t)kWaves * rpw * kRowsB;
+  auto load = [&](RowBatch& bt, int64_t j0) {
 #pragma unroll
     for (int q = 0; q < kRowsB; ++q) {
       const bool ok = j0 + q < hi;
       const int64_t j = ok ? j0 + q : hi - 1;     // in bounds, weight 0 past hi
-      rowp[q] = P + j * (int64_t)r;
-      t[q] = 0.0;
-      if (Dom::kVecStride == 2) {
-        ve[q] = vfin[j];
-        vm[q] = ok ? (double)vfin[m + j] : 0.0;
+      const float* row = P + j * (int64_t)r;
+#pragma unroll
+      for (int c = 0; c < kC; ++c) bt.x[q][c] = gld4s(row + coff[c]);
+      if (XR) {
+        bt.ve[q] = vfin[j];
+        bt.vm[q] = ok ? (double)vfin[m + j] : 0.0;
       } else {
-        ve[q] = 0.f;
-        vm[q] = ok ? (double)vfin[j] : 0.0;
+        bt.ve[q] = 0.f;
+        bt.vm[q] = ok ? (double)vfin[j] : 0.0;
       }
     }
-    for (int k0 = 0; k0 < r; k0 += 64 * kChunk) {
-      float x[kRowsB][kChunk];
+  };
+  auto sum = [&](const RowBatch& bt) {
+    double tq[kRowsB];
 #pragma unroll
-      for (int q = 0; q < kRowsB; ++q)
+    for (int q = 0; q < kRowsB; ++q) tq[q] = 0.0;
+    // branch-free: a column that is off (past r, or a zero column of z)
+    // has zk = 0 and a finite frame
 #pragma unroll
-        for (int c = 0; c < kChunk; ++c) {
-          const int k = k0 + lane + 64 * c;
-          x[q][c] = k < r ? rowp[q][k] : 0.f;
-        }
+    for (int c = 0; c < kC; ++c) {
 #pragma unroll
-      for (int c = 0; c < kChunk; ++c) {
-        const int k = k0 + lane + 64 * c;
-        if (k >= r) continue;
-        const double zk = zl[k];
-        if (Dom::kVecStride == 2) {
-          const float ze = z[k];
-          if (!(ze > -1.0e29f)) continue;        // a zero column of z
+      for (int e = 0; e < 4; ++e) {
+        const int k = coff[c] + e;
+        const float ze0 = XR ? zel[k] : 0.f;
+        const bool on = cv[c] && (!XR || ze0 > -1.0e29f);
+        const double zk = on ? zl[k] : 0.0;
+        const float ze = on ? ze0 : 0.f;
 #pragma unroll
-          for (int q = 0; q < kRowsB; ++q)
-            t[q] = fma(pow2_scaled(x[q][c], ve[q] + ze), zk, t[q]);
-        } else {
-#pragma unroll
-          for (int q = 0; q < kRowsB; ++q) t[q] = fma((double)x[q][c], zk, t[q]);
+        for (int q = 0; q < kRowsB; ++q) {
+          const float4& xq = bt.x[q][c];
+          const float xe = e == 0 ? xq.x : e == 1 ? xq.y : e == 2 ? xq.z : xq.w;
+          tq[q] = XR ? fma(pow2_scaled(xe, bt.ve[q] + ze), zk, tq[q])
+                     : fma((double)xe, zk, tq[q]);
         }
       }
     }
 #pragma unroll
-    for (int q = 0; q < kRowsB; ++q) tot = fma(t[q], vm[q], tot);
+    for (int q = 0; q < kRowsB; ++q) tot = fma(tq[q], bt.vm[q], tot);
+  };
+  int64_t j0 = lo + (int64_t)(wave * rpw + sub) * kRowsB;
+  if (!kPipe) {
+    for (; j0 < hi; j0 += stride) {
+      RowBatch A;
+      load(A, j0);
+      sum(A);
+    }
+  } else if (j0 < hi) {
+    RowBatch A, B;
+    load(A, j0);
+    for (;;) {
+      int64_t j1 = j0 + stride;
+      load(B, j1 < hi ? j1 : j0);
+      sum(A);
+      if (j1 >= hi) break;
+      j0 = j1;
+      j1 = j0 + stride;
+      load(A, j1 < hi ? j1 : j0);
+      sum(B);
+      if (j1 >= hi) break;
+      j0 = j1;
+    }
   }
+  }  // sweeps
   return block_dsum(tot, sh.d);
 }
 
@@ -1568,7 +1695,7 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
   // u^T K v in float64 (see dual_rows_pass): z64 partials into the slots
   double* myslot = reinterpret_cast<double*>(uniform_ptr(D.slots) +
                                              (int64_t)blockIdx.x * uniform_i32(D.slot_stride));
-  if (kf >= 1) dual_rows_pass<Dom>(D, rlo(), rhi(), myslot);
+  if (kf >= 1) dual_rows_pass<Dom>(D, rlo(), rhi(), myslot, lds);
   if (!group_barrier(B)) {
     if (br == 0 && threadIdx.x == 0) D.info->status = SK_ETIMEOUT;
     return;
@@ -1577,17 +1704,36 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
   // into the second w buffer (free once the final w is in place)
   double* z64 = reinterpret_cast<double*>(uniform_ptr(D.w2));
   if (kf >= 1) {
+    // columns [c0, c1) of this workgroup, nc at a time; the g partials of a
+    // column are split over Sn threads (seats split, split + Sn, ...) whose
+    // sums are then added in split order
     const int per = (r + g - 1) / g;
     const int c0 = br * per, c1 = min(r, c0 + per);
-    for (int k = c0 + threadIdx.x; k < c1; k += kBlock) {
+    double* L = reinterpret_cast<double*>(lds);
+    for (int cc = c0; cc < c1; cc += kBlock) {
+      const int nc = min(kBlock, c1 - cc);
+      const int Sn = kBlock / nc;
+      const int t = threadIdx.x;
+      const int split = t / nc;
+      const int k = cc + t % nc;
       double sacc = 0.0;
-      for (int b2 = 0; b2 < g; ++b2) {
-        const double* ps = reinterpret_cast<const double*>(
-            D.slots + (int64_t)cld(D.members + b2) * D.slot_stride);
-        sacc += cld(ps + k);
+      if (split < Sn) {
+        for (int b2 = split; b2 < g; b2 += Sn) {
+          const double* ps = reinterpret_cast<const double*>(
+              D.slots + (int64_t)cld(D.members + b2) * D.slot_stride);
+          sacc += cld(ps + k);
+        }
       }
-      cst(z64 + k, sacc);
+      __syncthreads();
+      L[t] = sacc;
+      __syncthreads();
+      if (t < nc) {
+        double tot = 0.0;
+        for (int sp = 0; sp < Sn; ++sp) tot += L[t + sp * nc];
+        cst(z64 + k, tot);
+      }
     }
+    __syncthreads();
   }
   if (!group_barrier(B)) {
     if (br == 0 && threadIdx.x == 0) D.info->status = SK_ETIMEOUT;
@@ -1596,10 +1742,15 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
   double ukv_blk = 0.0;
   if (kf >= 1) {
     double* zl = reinterpret_cast<double*>(lds);
+    float* zel = lds + 2 * r;
+    const float* zg = uniform_ptr(D.z);
     __syncthreads();
-    for (int k = threadIdx.x; k < r; k += kBlock) zl[k] = cld(z64 + k);
+    for (int k = threadIdx.x; k < r; k += kBlock) {
+      zl[k] = cld(z64 + k);
+      zel[k] = Dom::kVecStride == 2 ? zg[k] : 0.f;
+    }
     __syncthreads();
-    ukv_blk = dual_cols_pass<Dom>(D, clo(), chi(), vfin, zl, sh);
+    ukv_blk = dual_cols_pass<Dom>(D, clo(), chi(), vfin, zl, zel, sh);
   }
   if (threadIdx.x == 0) cst(D.dpart + 3 * g + br, ukv_blk);
   if (!group_barrier(B)) {
