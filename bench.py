@@ -341,8 +341,35 @@ def run_pixel_batch(args, torch, api, inputs):
     tol 1e-6, the float64 reductions and the gradient with respect to X.
     The timed region of a wave starts with its inputs resident (they are
     made on the device before it); `value` = problems / summed wave time."""
-    from paper_2006_07057_amd import batch
+    from paper_2006_07057_amd import autotune, batch
     probs, make = pixel_batch_problems(api, inputs, seed=args.seed)
+    tuning_src = "defaults"
+    tune_times = None
+    if args.autotune_out:
+        # tune each feature-count class on the median-size problem of that
+        # class (pixel generator, d = 784, eps = 10), 20 fixed iterations
+        by_r = {}
+        for p in probs:
+            by_r.setdefault(p.r, []).append(p)
+        shapes = []
+        for r, ps in sorted(by_r.items()):
+            ps = sorted(ps, key=lambda p: p.n + p.m)
+            mid = ps[len(ps) // 2]
+            shapes.append((mid.n, mid.m, r))
+        tune_times = {}
+        for (n, m, r) in shapes:
+            print(f"[bench] autotune class {autotune.class_of(r)} on ({n}, {m}, {r})",
+                  file=sys.stderr, flush=True)
+            t = autotune.tune_class(r, n, m, d=784, eps=10.0, kind="pixels", iters=20, reps=2)
+            tune_times[str(autotune.class_of(r))] = {f"{k[0]}:{k[1]}": round(v, 4)
+                                                      for k, v in sorted(t.items())}
+        autotune.save(args.autotune_out, notes={"workload": "pixels_batch256",
+                                               "shapes": shapes, "ms": tune_times})
+        tuning_src = args.autotune_out
+    elif args.tuning and args.tuning != "none" and os.path.exists(args.tuning):
+        autotune.load(args.tuning)
+        tuning_src = os.path.relpath(args.tuning, ROOT)
+    table = {str(c): list(autotune.current_table()[c]) for c in (512, 4096)}
     torch.cuda.empty_cache()
     free, total = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
@@ -414,11 +441,13 @@ def run_pixel_batch(args, torch, api, inputs):
                    "r": [512, 4096], "eps": 10.0, "n_m": "log-uniform [2^12, 2^20]",
                    "tol": 1e-6, "max_iter": 2000, "waves": len(waves),
                    "budget_bytes": budget,
+                   "tuning": {"source": tuning_src, "classes": table},
                    "step": "per wave: features + packed solves + fp64 reductions + dX"},
         "roofline": {"bound": K["bound"], "kernel": dom, "achieved": K["achieved"],
                      "peak": K["peak"], "unit": K["unit"], "frac": K["frac"],
                      "traffic": None},
         "kernels": kernels,
+        "autotune_ms": tune_times,
         "wall_s_per_step_with_input_generation": float(np.mean(walls)),
         "points_total": int(sum(p.n + p.m for p in probs)),
         "features_bytes_total": int(sum(4 * p.r * (p.n + p.m) for p in probs)),
@@ -706,6 +735,12 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=200_000)
+    ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2006_07057_amd",
+                                                     "tuning_pixels_batch256.json"),
+                    help="pixels_batch256: solver tuning table to load ('none': defaults)")
+    ap.add_argument("--autotune-out", default=None, metavar="PATH",
+                    help="pixels_batch256: tune each class on the batch's own shapes "
+                         "first and store the table at PATH")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     metavar="GIB", help="only run a plain device-to-device "
                     "copy of this many GiB, three times (the reference "

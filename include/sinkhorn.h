@@ -518,6 +518,27 @@ int sinkhorn_tune_set(int64_t r, int64_t target_bytes);
  * a negative value for an invalid r. */
 int64_t sinkhorn_tune_get(int64_t r);
 
+/* Lane layouts compiled for the solver class that serves r: writes up to
+ * `max` entries of four int32 (G lanes per feature row, C float4 chunks per
+ * lane with 4 G C the class's largest r, U rows per lane and batch, W waves
+ * per SIMD the kernels are compiled for) to out (host memory, may be NULL
+ * when max = 0) and returns the number of layouts of the class (variant 0,
+ * the default, first), or SK_EINVAL (negative) for r outside 1..SK_MAX_R.
+ * The layouts group the same sums differently: results differ by float32
+ * rounding only.  Host-only. */
+int32_t sinkhorn_solver_layouts(int64_t r, int32_t* out, int32_t max);
+
+/* Select lane layout `variant` (an index into sinkhorn_solver_layouts) for
+ * every later solve of the class serving r, in this process; 0 restores
+ * the default.  Written by the autotuner (host-only, not thread-safe
+ * against concurrent launches).  Errors: SK_EINVAL (r outside 1..SK_MAX_R,
+ * or no such variant). */
+int sinkhorn_tune_set_layout(int64_t r, int32_t variant);
+
+/* Layout variant in use for the class serving r, or a negative value for an
+ * invalid r. */
+int32_t sinkhorn_tune_get_layout(int64_t r);
+
 /* ------------------------------------------------------- instrumentation */
 /* Launch timing for measurement: with enable != 0, every later launch of
  * the solver (kind 0), feature (kind 1) and adjoint (kind 2) kernels is

@@ -117,6 +117,9 @@ SIGNATURES = {
                                                      c_void]),
     "sinkhorn_tune_set": (c_i32, [c_i64, c_i64]),
     "sinkhorn_tune_get": (c_i64, [c_i64]),
+    "sinkhorn_solver_layouts": (c_i32, [c_i64, c_void, c_i32]),
+    "sinkhorn_tune_set_layout": (c_i32, [c_i64, c_i32]),
+    "sinkhorn_tune_get_layout": (c_i32, [c_i64]),
     "sinkhorn_profile": (c_i32, [c_i32]),
     "sinkhorn_profile_read": (c_i32, [c_i32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(c_i64),

@@ -738,6 +738,29 @@ def tune_get(r: int) -> int:
     return v
 
 
+def solver_layouts(r: int):
+    """Lane layouts compiled for the solver class serving r, as a list of
+    (G, C, U, W) tuples; index = variant (0 is the default)."""
+    cnt = int(lib().sinkhorn_solver_layouts(int(r), None, 0))
+    if cnt < 0:
+        raise ValueError(f"no solver class for r={r}")
+    buf = (ctypes.c_int32 * (4 * max(cnt, 1)))()
+    lib().sinkhorn_solver_layouts(int(r), ctypes.cast(buf, ctypes.c_void_p), cnt)
+    return [tuple(int(buf[4 * i + k]) for k in range(4)) for i in range(cnt)]
+
+
+def tune_set_layout(r: int, variant: int):
+    """Select the lane layout variant of the solver class serving r."""
+    check(lib().sinkhorn_tune_set_layout(int(r), int(variant)), "sinkhorn_tune_set_layout")
+
+
+def tune_get_layout(r: int) -> int:
+    v = int(lib().sinkhorn_tune_get_layout(int(r)))
+    if v < 0:
+        raise ValueError(f"no solver class for r={r}")
+    return v
+
+
 # ------------------------------------------------------- instrumentation
 PROF_SOLVER, PROF_FEATURES, PROF_ADJOINT = 0, 1, 2
 

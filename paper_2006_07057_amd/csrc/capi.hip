@@ -100,6 +100,13 @@ std::map<int, int64_t>& tuning_table() {
 
 int class_rmax(int r) { return solver_class_rmax(r); }
 
+// Lane layout variant per solver class (indexed like tuning_table); absent
+// means variant 0.  Set by the autotuner.
+std::map<int, int>& layout_table() {
+  static std::map<int, int> t;
+  return t;
+}
+
 constexpr int64_t kDefaultTarget = 256 * 1024;
 constexpr int64_t kMaxRowsPerLane = 256;            // see run_solves
 constexpr int64_t kSideBySideBytes = 256ll << 20;   // feature bytes per iteration
@@ -483,6 +490,11 @@ int specs_from(const sk_solve_spec* in, int32_t count,
 
 }  // namespace
 
+int sk::solver_layout_variant(int rmax) {
+  auto it = layout_table().find(rmax);
+  return it != layout_table().end() ? it->second : 0;
+}
+
 extern "C" {
 
 const char* sinkhorn_strerror(int status) {
@@ -795,6 +807,28 @@ int64_t sinkhorn_tune_get(int64_t r) {
   if (cls <= 0) return -1;
   auto it = tuning_table().find(cls);
   return it != tuning_table().end() ? it->second : kDefaultTarget;
+}
+
+int32_t sinkhorn_solver_layouts(int64_t r, int32_t* out, int32_t max) {
+  if (r < 1 || r > SK_MAX_R || max < 0) return SK_EINVAL;
+  return solver_layouts((int)r, out, max);
+}
+
+int sinkhorn_tune_set_layout(int64_t r, int32_t variant) {
+  if (r < 1 || r > SK_MAX_R) return SK_EINVAL;
+  const int cls = class_rmax((int)r);
+  if (cls <= 0 || variant < 0 || variant >= solver_layouts((int)r, nullptr, 0))
+    return SK_EINVAL;
+  if (variant == 0) layout_table().erase(cls);
+  else layout_table()[cls] = variant;
+  return SK_OK;
+}
+
+int32_t sinkhorn_tune_get_layout(int64_t r) {
+  if (r < 1 || r > SK_MAX_R) return -1;
+  const int cls = class_rmax((int)r);
+  if (cls <= 0) return -1;
+  return solver_layout_variant(cls);
 }
 
 int sinkhorn_state_layout(int64_t n, int64_t m, int64_t r,

@@ -73,6 +73,16 @@ int solver_class_lanes(int r);
 // error).
 int solver_capacity(int r, int xr);
 
+// Lane layouts of the solver class serving r: writes up to `max` entries
+// of (G lanes per row, C float4 per lane, U rows per lane and batch, W
+// waves per SIMD) into out (4 ints each) and returns how many the class
+// has (variant 0 first: the default).
+int solver_layouts(int r, int32_t* out, int max);
+
+// Layout variant in use for the class whose largest r is rmax (the tuning
+// table's entry, 0 by default); the solver's class lookups read it.
+int solver_layout_variant(int rmax);
+
 // Copy host bytes to device memory with stream-ordered kernel launches
 // (the bytes travel as kernel arguments), so the copy can be graph-captured
 // and the host buffer may be reused as soon as the call returns.

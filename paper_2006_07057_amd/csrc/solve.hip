@@ -1838,6 +1838,8 @@ __global__ void upload_kernel(unsigned char* dst, UploadPayload p, int nbytes) {
 // ----------------------------------------------------------- dispatch table
 struct SolverClass {
   int rmax;             // largest r of the class
+  int variant;          // lane layout variant (0: the default)
+  int G, C, U, W;       // lanes per row, float4 per lane, rows per batch, waves per SIMD
   int lanes;            // lanes per feature row (G, both domains)
   const void* fn[2];    // kernel symbols: linear, extended range
   void (*launch[2])(dim3, hipStream_t, const SolveDesc*, int, int, LaunchCtl*,
@@ -1854,38 +1856,59 @@ void launch_cls(dim3 grid, hipStream_t s, const SolveDesc* d, int count,
 }
 
 // A class serves every r <= rmax with one linear and one extended-range
-// kernel; each kernel's lane layout (G lanes per row, C float4 per lane, so
-// 4 G C >= rmax), batch depth U, r-vector placement VL and occupancy W.
-#define SK_CLASS(RMAX, LG, LC, LU, LV, LW, XG, XC, XU, XV, XW)                        \
-  {RMAX, LG,                                                                        \
-   {reinterpret_cast<const void*>(&solver_kernel<LinearDomain<LG, LC, LU, LV, LW>, false>), \
-    reinterpret_cast<const void*>(&solver_kernel<XRangeDomain<XG, XC, XU, XV, XW>, false>)}, \
-   {&launch_cls<LinearDomain<LG, LC, LU, LV, LW>>,                                   \
-    &launch_cls<XRangeDomain<XG, XC, XU, XV, XW>>},                                  \
-   &launch_cls<XRangeDomain<XG, XC, XU, XV, XW>, true>}
+// kernel per lane layout: G lanes per row, C float4 chunks per lane
+// (4 G C = rmax), batch depth U, r-vector in LDS (VL) and occupancy W
+// (waves per SIMD the kernel is compiled for).  Variant 0 is the default;
+// the others are alternatives the autotuner may select per class (fewer
+// registers per lane for a second wave per SIMD, or more lanes per row).
+#define SK_CLASS(RMAX, VAR, G_, C_, U_, VL_, W_)                                       \
+  {RMAX, VAR, G_, C_, U_, W_, G_,                                                    \
+   {reinterpret_cast<const void*>(&solver_kernel<LinearDomain<G_, C_, U_, VL_, W_>, false>), \
+    reinterpret_cast<const void*>(&solver_kernel<XRangeDomain<G_, C_, U_, VL_, W_>, false>)}, \
+   {&launch_cls<LinearDomain<G_, C_, U_, VL_, W_>>,                                  \
+    &launch_cls<XRangeDomain<G_, C_, U_, VL_, W_>>},                                 \
+   &launch_cls<XRangeDomain<G_, C_, U_, VL_, W_>, true>}
 
 const SolverClass kClasses[] = {
-    SK_CLASS(4, 1, 1, 2, true, 4, 1, 1, 2, true, 4),
-    SK_CLASS(8, 1, 2, 2, true, 2, 1, 2, 2, true, 2),
-    SK_CLASS(16, 1, 4, 2, true, 2, 1, 4, 2, true, 2),
-    SK_CLASS(32, 1, 8, 2, true, 1, 1, 8, 2, true, 1),
-    SK_CLASS(64, 2, 8, 2, true, 1, 2, 8, 2, true, 1),
-    SK_CLASS(128, 4, 8, 2, true, 1, 4, 8, 2, true, 1),
-    SK_CLASS(256, 8, 8, 2, true, 1, 8, 8, 2, true, 1),
-    SK_CLASS(512, 16, 8, 2, true, 1, 16, 8, 2, true, 1),
-    SK_CLASS(768, 32, 6, 2, true, 1, 32, 6, 2, true, 1),
-    SK_CLASS(1024, 32, 8, 2, true, 1, 32, 8, 2, true, 1),
-    SK_CLASS(1536, 64, 6, 2, true, 1, 64, 6, 2, true, 1),
-    SK_CLASS(2048, 64, 8, 2, true, 1, 64, 8, 2, true, 1),
-    SK_CLASS(3072, 64, 12, 1, false, 1, 64, 12, 1, false, 1),
-    SK_CLASS(4096, 64, 16, 1, false, 1, 64, 16, 1, false, 1),
+    SK_CLASS(4, 0, 1, 1, 2, true, 4),
+    SK_CLASS(8, 0, 1, 2, 2, true, 2),
+    SK_CLASS(16, 0, 1, 4, 2, true, 2),
+    SK_CLASS(32, 0, 1, 8, 2, true, 1),
+    SK_CLASS(64, 0, 2, 8, 2, true, 1),
+    SK_CLASS(64, 1, 4, 4, 2, true, 2),
+    SK_CLASS(128, 0, 4, 8, 2, true, 1),
+    SK_CLASS(256, 0, 8, 8, 2, true, 1),
+    SK_CLASS(256, 1, 16, 4, 2, true, 2),
+    SK_CLASS(512, 0, 16, 8, 2, true, 1),
+    SK_CLASS(512, 1, 32, 4, 2, true, 2),
+    SK_CLASS(768, 0, 32, 6, 2, true, 1),
+    SK_CLASS(1024, 0, 32, 8, 2, true, 1),
+    SK_CLASS(1024, 1, 64, 4, 2, true, 2),
+    SK_CLASS(1536, 0, 64, 6, 2, true, 1),
+    SK_CLASS(2048, 0, 64, 8, 2, true, 1),
+    SK_CLASS(3072, 0, 64, 12, 1, false, 1),
+    SK_CLASS(4096, 0, 64, 16, 1, false, 1),
 };
 constexpr int kNumClasses = sizeof(kClasses) / sizeof(kClasses[0]);
 
+// The class entry for r: the smallest rmax >= r, in the layout variant the
+// tuning table names for it (the default when that variant does not exist).
 const SolverClass* class_for(int r) {
+  int rmax = 0;
   for (int i = 0; i < kNumClasses; ++i)
-    if (r <= kClasses[i].rmax) return &kClasses[i];
-  return nullptr;
+    if (r <= kClasses[i].rmax) {
+      rmax = kClasses[i].rmax;
+      break;
+    }
+  if (rmax == 0) return nullptr;
+  const int want = solver_layout_variant(rmax);
+  const SolverClass* base = nullptr;
+  for (int i = 0; i < kNumClasses; ++i) {
+    if (kClasses[i].rmax != rmax) continue;
+    if (kClasses[i].variant == 0 && !base) base = &kClasses[i];
+    if (kClasses[i].variant == want) return &kClasses[i];
+  }
+  return base;
 }
 
 uint64_t timeout_ticks() {
@@ -1911,6 +1934,26 @@ int solver_class_rmax(int r) {
 int solver_class_lanes(int r) {
   const SolverClass* cls = class_for(r);
   return cls ? cls->lanes : 0;
+}
+
+int solver_layouts(int r, int32_t* out, int max) {
+  const SolverClass* cls = class_for(r);
+  if (!cls) return 0;
+  int cnt = 0;
+  for (int v = 0;; ++v) {
+    const SolverClass* hit = nullptr;
+    for (int i = 0; i < kNumClasses; ++i)
+      if (kClasses[i].rmax == cls->rmax && kClasses[i].variant == v) hit = &kClasses[i];
+    if (!hit) break;
+    if (out && cnt < max) {
+      out[4 * cnt + 0] = hit->G;
+      out[4 * cnt + 1] = hit->C;
+      out[4 * cnt + 2] = hit->U;
+      out[4 * cnt + 3] = hit->W;
+    }
+    ++cnt;
+  }
+  return cnt;
 }
 
 int solver_capacity(int r, int xr) {

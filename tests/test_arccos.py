@@ -33,6 +33,9 @@ def _data(seed, n, m, d, r, sigma):
 @pytest.mark.gpu
 @pytest.mark.parametrize("s", [0, 1, 2])
 @pytest.mark.parametrize("d,r", [(3, 127), (16, 255), (2, 1023),
+                                 # per-row kernel reading anchors from global
+                                 # memory (d (r + 1) > 12288 floats of staging)
+                                 (7, 2047),
                                  # matrix-core projections (d >= 8, d % 4 == 0):
                                  # r + 1 = 101 columns (unaligned rows), pixel width,
                                  # 16 column blocks

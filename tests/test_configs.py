@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from paper_2006_07057_amd import inputs
-from parity import check_divergence, check_gradient, float32_wbar_floor
+from parity import check_divergence, check_gradient
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
@@ -137,10 +137,8 @@ def test_otgan_shaped_gradients_and_descent(api):
     Pf, sf = oracle.gaussian_features_scaled(Xf, U, eps, q)
     reff = _oracle_div(Xf, c.Y, c.a, c.b, U, eps, q, (Pf, sf, Py, sy))
     # after the descent W_bar (about 2e-5) is 1e-6 of the terms it is the
-    # difference of, so 1e-5 of it (2e-10) is below the float32 resolution
-    # of the dual sums: the float32 floor applies (derived in parity.py)
-    check_divergence("otgan-shaped after 50 steps", _host(o), reff,
-                     wbar_floor=float32_wbar_floor(eps, c.a, c.b))
+    # difference of; the dual objective keeps it within 1e-5 all the same
+    check_divergence("otgan-shaped after 50 steps", _host(o), reff)
 
 
 def test_mixed_pixel_batch_under_autotuner(api):

@@ -27,16 +27,34 @@ def test_table_save_load_roundtrip(tmp_path):
     table = {256: 512 << 10, 1024: 4 << 20}
     p = str(tmp_path / "tune.json")
     with open(p, "w") as f:
+        # a table written before layouts were tuned: targets only
         json.dump({"device": None, "targets": {str(k): v for k, v in table.items()}}, f)
-    assert autotune.load(p) == table
+    assert autotune.load(p) == {256: (0, 512 << 10), 1024: (0, 4 << 20)}
     assert api.tune_get(200) == 512 << 10      # same class as 256
     assert api.tune_get(1000) == 4 << 20
     assert api.tune_get(64) == default
+    with open(p, "w") as f:
+        json.dump({"targets": {"1024": 4 << 20}, "layouts": {"1024": 1}}, f)
+    assert autotune.load(p) == {1024: (1, 4 << 20)}
+    assert api.tune_get_layout(1000) == 1 and api.tune_get_layout(512) == 0
     autotune.save(str(tmp_path / "again.json"))
-    back = json.load(open(tmp_path / "again.json"))["targets"]
-    assert int(back["256"]) == 512 << 10 and int(back["64"]) == default
+    back = json.load(open(tmp_path / "again.json"))
+    assert int(back["targets"]["256"]) == 512 << 10 and int(back["targets"]["64"]) == default
+    assert int(back["layouts"]["1024"]) == 1 and int(back["layouts"]["256"]) == 0
     autotune.reset()
-    assert api.tune_get(256) == default
+    assert api.tune_get(256) == default and api.tune_get_layout(1024) == 0
+
+
+def test_layouts_per_class():
+    """Every class lists its compiled lane layouts, the default first, each
+    covering the class's largest r (4 G C = rmax)."""
+    from paper_2006_07057_amd import api
+    for c in autotune.CLASS_RMAX:
+        lays = api.solver_layouts(c)
+        assert len(lays) >= 1
+        for (G, C, U, W) in lays:
+            assert 4 * G * C == c and 64 % G == 0 and U >= 1 and W >= 1
+    assert len(api.solver_layouts(512)) == 2 and len(api.solver_layouts(1024)) == 2
 
 
 def test_table_rejects_bad_entries(tmp_path):
@@ -46,10 +64,19 @@ def test_table_rejects_bad_entries(tmp_path):
         json.dump({"targets": {"100": 1024}}, f)   # not a class
     with pytest.raises(ValueError):
         autotune.load(p)
+    with open(p, "w") as f:
+        json.dump({"targets": {"4096": 1024}, "layouts": {"4096": 3}}, f)   # no such layout
+    with pytest.raises(ValueError):
+        autotune.load(p)
+    autotune.reset()
     with pytest.raises(Exception):
         api.tune_set(5000, 1024)
     with pytest.raises(Exception):
         api.tune_set(64, -1)
+    with pytest.raises(Exception):
+        api.tune_set_layout(4096, 1)
+    with pytest.raises(Exception):
+        api.tune_set_layout(512, -1)
 
 
 # ------------------------------------------------------------------- GPU
@@ -142,11 +169,43 @@ def test_autotune_changes_timing_not_results():
     ref = api.solve(Px, Py, a, b, fixed_iter=30)
     ref_u = api.host_log_scaling(ref.u, api.EXTENDED)
     times = autotune.tune_class(r, n, candidates=(64 << 10, 256 << 10, 4 << 20), iters=10)
-    assert set(times) == {64 << 10, 256 << 10, 4 << 20}
+    assert set(times) == {(0, 64 << 10), (0, 256 << 10), (0, 4 << 20)}
     assert all(t > 0 for t in times.values())
-    assert api.tune_get(r) == min(times, key=times.get)
+    assert (api.tune_get_layout(r), api.tune_get(r)) == min(times, key=times.get)
     got = api.solve(Px, Py, a, b, fixed_iter=30)
     got_u = api.host_log_scaling(got.u, api.EXTENDED)
     np.testing.assert_allclose(got_u, ref_u, rtol=0, atol=2e-5)
     assert got.info()["w_hat"] == pytest.approx(ref.info()["w_hat"], rel=1e-6)
     autotune.reset()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("r", [64, 200, 512, 1024])
+@pytest.mark.parametrize("rng", [0, 1])
+def test_alternative_layouts_match_oracle(r, rng):
+    """Each compiled lane layout other than the default, selected through
+    the tuning table, gives the oracle's divergence (Eq. reg-sdiv) within
+    1e-5 at 100 fixed iterations, and the default's result to float32
+    rounding; both numeric domains, several workgroups per solve."""
+    import torch
+    from paper_2006_07057_amd import api
+    from parity import check_divergence
+    n, m, d, eps = 3000, 2500, 3, 0.5
+    X, Y, a, b, U = _inputs(11, n, m, d, r)
+    q = oracle.q_from_sigma2(1.0, eps)
+    t = lambda x: torch.from_numpy(x).cuda()
+    args = (t(X), t(Y), t(a), t(b), t(U), eps, q)
+    ref = oracle.divergence_scaled(X, Y, a, b, U.astype(np.float64), eps, q, fixed_iter=100)
+    autotune.reset()
+    api.tune_set(r, 16 << 10)              # several workgroups per solve
+    try:
+        base, _ = api.divergence(*args, fixed_iter=100, range=rng)
+        base = base.cpu().numpy()
+        for v in range(1, len(api.solver_layouts(r))):
+            api.tune_set_layout(r, v)
+            out, _ = api.divergence(*args, fixed_iter=100, range=rng)
+            out = out.cpu().numpy()
+            check_divergence(f"layout {api.solver_layouts(r)[v]} r={r} range={rng}", out, ref)
+            np.testing.assert_allclose(out[1:], base[1:], rtol=1e-6)
+    finally:
+        autotune.reset()

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from paper_2006_07057_amd import inputs
-from parity import check_divergence, check_gradient, float32_wbar_floor
+from parity import check_divergence, check_gradient
 
 HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
@@ -73,7 +73,7 @@ def test_pixel_batch256_in_waves_matches_oracle():
     """All 256 problems run (several waves within 70% of free HBM); every
     solve converges; the six sampled problems with n, m <= 2^17 match the
     stored float64 oracle values: W_bar and the three estimates within
-    1e-5 (W_bar with the float32 floor where it is nearly zero), the
+    1e-5 (problem 199's W_bar is 4.4e-6 of its terms), the
     gradient with respect to X on 8 sampled rows within 1e-4 and its norm within
     1e-4, iteration counts within one."""
     import torch
@@ -115,10 +115,7 @@ def test_pixel_batch256_in_waves_matches_oracle():
     for i, (out, iters, grow, gnorm) in sorted(seen.items()):
         g = gold["problems"][str(i)]
         lab = f"pixel batch256 problem {i} ({g['n']}, {g['m']}, {g['r']})"
-        a = np.full(g["n"], 1.0 / g["n"])
-        b = np.full(g["m"], 1.0 / g["m"])
-        check_divergence(lab, out, (g["W_bar"], g["W_xy"], g["W_xx"], g["W_yy"]),
-                         wbar_floor=float32_wbar_floor(gold["eps"], a, b))
+        check_divergence(lab, out, (g["W_bar"], g["W_xy"], g["W_xx"], g["W_yy"]))
         assert all(abs(x - y) <= 1 for x, y in zip(iters, g["iters"])), (i, iters, g["iters"])
         check_gradient(lab + " dX[8 rows]", grow, np.asarray(g["grad_x_rows"]))
         assert abs(gnorm - g["grad_x_norm"]) <= 1e-4 * g["grad_x_norm"], (i, gnorm)
