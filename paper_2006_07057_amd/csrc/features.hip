@@ -209,29 +209,13 @@ constexpr int kMfmaCols = 64;
 constexpr int kMfmaK = 32;
 constexpr int kMfmaPad = 36;  // floats per LDS row (bank spread)
 
-// c_k of the columns, written by anchor_cterm_kernel before each MFMA launch
-// (launches on one device run one after another on their stream).
-__device__ float g_anchor_cval[SK_MAX_R];
-
 // Anchor terms c_k = c0 + cu ||u_k||^2 (Gaussian map: c0 = -log(r)/2 +
-// (d/4) log(2q), cu = 1/(eps q) - 2/eps; arc-cosine map: its own c0, cu),
-// formed in float64 and rounded once.  One wave per anchor: lanes take
-// coordinates e = lane, lane + 64, ... (coalesced), then a butterfly in a
-// fixed order.
-__global__ void __launch_bounds__(kBlock)
-anchor_cterm_kernel(const float* __restrict__ U, int r, int d, double c0, double cu) {
-  const int k = blockIdx.x * kWaves + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (k >= r) return;   // whole waves leave together
-  double un = 0.0;
-  for (int e = lane; e < d; e += 64) {
-    const double v = U[(int64_t)k * d + e];
-    un += v * v;
-  }
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) un += __shfl_xor(un, off, 64);
-  if (lane == 0) g_anchor_cval[k] = (float)(c0 + cu * un);
-}
+// (d/4) log(2q), cu = 1/(eps q) - 2/eps; arc-cosine map: its own c0, cu)
+// are formed inside the kernel: wave t sums the squares of the coordinates
+// of columns 16 t .. 16 t + 15 that it reads for its products, in float64,
+// chunk by chunk in k order, the four k groups are added by lane
+// exchanges, and the column block's 64 norms pass through LDS, so every
+// workgroup computes the same c_k (no table shared between launches).
 
 constexpr int kMfmaTilePad = 68;  // floats per row of the LDS transpose tile
 
@@ -247,7 +231,8 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
                      float scale, float neg2e, int s_exp, float lk,
                      float* __restrict__ Phi, float* __restrict__ logscale,
                      const float* __restrict__ X2, int64_t n2,
-                     float* __restrict__ Phi2, float* __restrict__ logscale2) {
+                     float* __restrict__ Phi2, float* __restrict__ logscale2,
+                     double c0, double cu) {
   constexpr bool LOG2 = MODE == 1;
   if (blockIdx.y == 1) {
     X = X2;
@@ -262,6 +247,7 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
   __shared__ __align__(16) float sB[2][kMfmaCols * kMfmaPad];
   __shared__ float s_xn[kMfmaRows];
   __shared__ float s_max[kMfmaRows];
+  __shared__ double s_un[kMfmaCols];
   static_assert(kWaves * 16 * kMfmaTilePad <= 2 * kMfmaRows * kMfmaPad,
                 "transpose tiles fit in the A staging buffers");
   const int tid = threadIdx.x;
@@ -310,6 +296,7 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
 
   for (int cb = 0; cb < W; cb += kMfmaCols) {
     f4v acc[4];
+    double un = 0.0;   // partial ||u||^2 of column 16 wave + l16 over this lane's k
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
     f4v ra[2], rb[2];
@@ -333,6 +320,10 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
         const float* B = &sB[buf][(16 * t + l16) * kMfmaPad + 8 * q];
         const f4v b0 = *reinterpret_cast<const f4v*>(B);
         const f4v b1 = *reinterpret_cast<const f4v*>(B + 4);
+        if (t == wave)
+          un += (double)b0.x * b0.x + (double)b0.y * b0.y + (double)b0.z * b0.z +
+                (double)b0.w * b0.w + (double)b1.x * b1.x + (double)b1.y * b1.y +
+                (double)b1.z * b1.z + (double)b1.w * b1.w;
 #pragma unroll
         for (int e = 0; e < 4; ++e)
           acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[e], b0[e], acc[t], 0, 0, 0);
@@ -345,10 +336,14 @@ features_mfma_kernel(const float* __restrict__ X, int64_t n, int d,
     }
     // lane holds acc[t][v] = x_{row_base + 4q + v} . u_{cb + 16t + l16};
     // D goes through the wave's LDS tile (row 4q + v, column 16t + l16)
+    un += __shfl_xor(un, 16, 64);   // the four k groups of column 16 wave + l16
+    un += __shfl_xor(un, 32, 64);
+    if (q == 0) s_un[16 * wave + l16] = un;
+    __syncthreads();
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int col = cb + 16 * t + l16;
-      const float cval = col < r ? g_anchor_cval[col] : 0.f;
+      const float cval = col < r ? (float)(c0 + cu * s_un[16 * t + l16]) : 0.f;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         float Dv;
@@ -449,16 +444,12 @@ hipError_t launch_mfma(const FeatDesc& D, hipStream_t s, const FeatDesc* D2 = nu
   const double cu = 1.0 / (eps * q) - 2.0 / eps;
   const float scale = (float)(4.0 / eps);
   const float neg2e = (float)(-2.0 / eps);
-  hipLaunchKernelGGL(anchor_cterm_kernel, dim3((D.r + kWaves - 1) / kWaves), dim3(kBlock), 0, s,
-                     D.U, D.r, D.d, c0, cu);
-  const hipError_t e0 = hipGetLastError();
-  if (e0 != hipSuccess) return e0;
   if (D.log2_out)
     hipLaunchKernelGGL(features_mfma_kernel<1>, grid, dim3(kBlock), 0, s, D.X, D.n, D.d,
-                       D.U, D.r, scale, neg2e, 0, 0.f, D.Phi, D.s, X2, n2, Phi2, s2);
+                       D.U, D.r, scale, neg2e, 0, 0.f, D.Phi, D.s, X2, n2, Phi2, s2, c0, cu);
   else
     hipLaunchKernelGGL(features_mfma_kernel<0>, grid, dim3(kBlock), 0, s, D.X, D.n, D.d,
-                       D.U, D.r, scale, neg2e, 0, 0.f, D.Phi, D.s, X2, n2, Phi2, s2);
+                       D.U, D.r, scale, neg2e, 0, 0.f, D.Phi, D.s, X2, n2, Phi2, s2, c0, cu);
   return hipGetLastError();
 }
 
@@ -751,15 +742,10 @@ hipError_t launch_features_arccos(const float* X, int64_t n, int d, const float*
     const int64_t blocks = (n + kMfmaRows - 1) / kMfmaRows;
     if (blocks > 0x7fffffff || r + 1 > SK_MAX_R) return hipErrorInvalidValue;
     void* tok = prof_begin(kProfFeatures, s);
-    hipLaunchKernelGGL(anchor_cterm_kernel, dim3((r + kWaves - 1) / kWaves), dim3(kBlock), 0,
-                       s, U, r, d, (double)c0, (double)cu);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) {
-      hipLaunchKernelGGL(features_mfma_kernel<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                         X, n, d, U, r, 1.0f, 0.f, s_exp, lk, Phi, logscale, nullptr,
-                         (int64_t)0, nullptr, nullptr);
-      e = hipGetLastError();
-    }
+    hipLaunchKernelGGL(features_mfma_kernel<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                       X, n, d, U, r, 1.0f, 0.f, s_exp, lk, Phi, logscale, nullptr,
+                       (int64_t)0, nullptr, nullptr, (double)c0, (double)cu);
+    const hipError_t e = hipGetLastError();
     prof_end(tok, s);
     return e;
   }
