@@ -361,7 +361,10 @@ def test_acc_divergence_matches_converged_oracle(n, m, d, r, eps):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("seed,n,m,d,r,eps,steps", [(556, 300, 250, 3, 256, 0.7, 30),
-                                                    (1132, 1000, 900, 2, 128, 0.5, 35)])
+                                                    (1132, 1000, 900, 2, 128, 0.5, 35),
+                                                    # a long trajectory (about 120
+                                                    # gradient evaluations per solve)
+                                                    (32, 300, 260, 2, 128, 1.0, 64)])
 def test_acc_divergence_gradients_match_oracle(seed, n, m, d, r, eps, steps):
     """After a fixed number of accepted steps, the three dual points, the
     dual values and the adjoint's gradients (dX, da, dY, db) match the
