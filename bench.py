@@ -366,9 +366,12 @@ def run_pixel_batch(args, torch, api, inputs):
         autotune.save(args.autotune_out, notes={"workload": "pixels_batch256",
                                                "shapes": shapes, "ms": tune_times})
         tuning_src = args.autotune_out
-    elif args.tuning and args.tuning != "none" and os.path.exists(args.tuning):
-        autotune.load(args.tuning)
-        tuning_src = os.path.relpath(args.tuning, ROOT)
+    else:
+        path = args.tuning or os.path.join(ROOT, "paper_2006_07057_amd",
+                                           "tuning_pixels_batch256.json")
+        if path != "none" and os.path.exists(path):
+            autotune.load(path)
+            tuning_src = os.path.relpath(path, ROOT)
     table = {str(c): list(autotune.current_table()[c]) for c in (512, 4096)}
     torch.cuda.empty_cache()
     free, total = torch.cuda.mem_get_info()
@@ -554,41 +557,59 @@ def run_accelerated(args, wl, torch, api, X, Y, a, b, U, q):
     return 0
 
 
-def plain_stream(torch, api, reqs, tol=1e-6, max_iter=2000, check_every=10):
-    """Comparator for the serving path: one problem at a time, textbook
-    Sinkhorn on the factored kernel with torch matrix-vector products
-    (v = b / (Py (Px^T u)), u = a / (Px (Py^T v))), features from the library
-    in the linear layout, the L1 column-marginal stop test every
-    `check_every` iterations (one host synchronisation each), the same
-    tolerance and cap.  Returns (seconds, [W_bar or nan per request])."""
+def plain_stream(torch, api, reqs, tol=1e-6, max_iter=2000, check_every=10,
+                 dense_bytes=2 << 30):
+    """Comparator for the serving path (the paper's plain Sinkhorn on the
+    kernel matrix): one problem at a time, the dense K = Phi_x Phi_y^T formed
+    on the device (features from the library in the linear layout) when it
+    takes at most `dense_bytes`, else the factored products; textbook
+    Sinkhorn v = b / K^T u, u = a / K v with torch matrix-vector products,
+    the L1 column-marginal stop test every `check_every` iterations (one
+    host synchronisation each), the same tolerance and cap.  Its own float64
+    dual estimates and W_bar (it is a separate implementation).  Returns
+    (seconds, [W_bar or nan per request], solves run on a dense K)."""
     import math
     dev = torch.device("cuda:0")
     t = lambda x: torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
     out = []
+    n_dense = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for q in reqs:
+    for qi, q in enumerate(reqs):
+        if qi % 16 == 0:
+            print(f"[bench] plain Sinkhorn: request {qi}/{len(reqs)}", file=sys.stderr,
+                  flush=True)
         X, Y, a, b, U = t(q.X), t(q.Y), t(q.a), t(q.b), t(q.U)
         Px, sx = api.features(X, U, q.eps, q.q, range=api.LINEAR)
         Py, sy = api.features(Y, U, q.eps, q.q, range=api.LINEAR)
         ws = []
         for (P, Q, p, w, sp, sq) in ((Px, Py, a, b, sx, sy), (Px, Px, a, a, sx, sx),
                                       (Py, Py, b, b, sy, sy)):
+            if P.shape[0] * Q.shape[0] * 4 <= dense_bytes:
+                K = P @ Q.t()
+                Kv = lambda v: K @ v
+                Ktu = lambda u: K.t() @ u
+                n_dense += 1
+            else:
+                K = None
+                Kv = lambda v, P=P, Q=Q: P @ (Q.t() @ v)
+                Ktu = lambda u, P=P, Q=Q: Q @ (P.t() @ u)
             u = torch.ones_like(p)
             v = w
             for it in range(1, max_iter + 1):
-                v = w / (Q @ (P.t() @ u))
-                u = p / (P @ (Q.t() @ v))
+                v = w / Ktu(u)
+                u = p / Kv(v)
                 if it % check_every == 0 or it == max_iter:
-                    err = float((v * (Q @ (P.t() @ u)) - w).abs().sum().item())
+                    err = float((v * Ktu(u) - w).abs().sum().item())
                     if not math.isfinite(err) or err < tol:
                         break
+            del K
             wh = q.eps * (torch.dot(p.double(), torch.log(u.double()) - sp.double()) +
                           torch.dot(w.double(), torch.log(v.double()) - sq.double()))
             ws.append(float(wh.item()))
         out.append(ws[0] - 0.5 * (ws[1] + ws[2]))
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, out
+    return time.perf_counter() - t0, out, n_dense
 
 
 def run_stream(args, torch, api, inputs):
@@ -606,6 +627,34 @@ def run_stream(args, torch, api, inputs):
         if (i + 1) % 256 == 0:
             print(f"[bench] materialised {i + 1}/{len(specs)} requests",
                   file=sys.stderr, flush=True)
+    from paper_2006_07057_amd import autotune
+    tuning_src = "defaults"
+    tune_times = None
+    if args.autotune_out:
+        # tune each feature-count class on the request of median size among
+        # those of that r (its own d and eps; the stream's generator), 20
+        # fixed iterations
+        by_r = {}
+        for sp in specs:
+            by_r.setdefault(sp.r, []).append(sp)
+        tune_times = {}
+        for r, sps in sorted(by_r.items()):
+            sps = sorted(sps, key=lambda sp: sp.n + sp.m)
+            mid = sps[len(sps) // 2]
+            print(f"[bench] autotune class {autotune.class_of(r)} on request {mid.rid} "
+                  f"(n={mid.n}, m={mid.m}, d={mid.d}, eps={mid.eps})",
+                  file=sys.stderr, flush=True)
+            t = autotune.tune_class(r, mid.n, mid.m, d=mid.d, eps=mid.eps, iters=20,
+                                    reps=2, seed=mid.seed)
+            tune_times[str(autotune.class_of(r))] = {f"{k[0]}:{k[1]}": round(v, 4)
+                                                      for k, v in sorted(t.items())}
+        autotune.save(args.autotune_out, notes={"workload": "stream", "ms": tune_times})
+        tuning_src = args.autotune_out
+    else:
+        path = args.tuning or os.path.join(ROOT, "paper_2006_07057_amd", "tuning_stream.json")
+        if path != "none" and os.path.exists(path):
+            autotune.load(path)
+            tuning_src = os.path.relpath(path, ROOT)
     # warm the kernels and the allocator on two small requests
     warm = serve.Server(epoch_iters=args.epoch_iters)
     warm.run([serve.from_spec(sp) for sp in inputs.request_stream(
@@ -655,7 +704,11 @@ def run_stream(args, torch, api, inputs):
                    "tol": 1e-6, "max_iter": 2000, "epoch_iters": args.epoch_iters,
                    "target_bytes_per_workgroup": {str(c): api.tune_get(c)
                                                   for c in (64, 256, 1024)},
+                   "tuning": {"source": tuning_src,
+                              "classes": {str(c): list(autotune.current_table()[c])
+                                          for c in (64, 256, 1024)}},
                    "hbm_budget_bytes": srv.budget},
+        "autotune_ms": tune_times,
         "latency_ms": {"p50": st["p50_ms"], "p99": st["p99_ms"]},
         "completed": st["ok"],
         "failed": {str(k): v for k, v in st["failed"].items()},
@@ -683,7 +736,7 @@ def run_stream(args, torch, api, inputs):
         res2 = srv2.run(sub)
         torch.cuda.synchronize()
         ours_s = time.perf_counter() - t0
-        plain_s, plain_w = plain_stream(torch, api, sub)
+        plain_s, plain_w, plain_dense = plain_stream(torch, api, sub)
         ours = {r.rid: r for r in res2}
         both = [(ours[j].w_bar, plain_w[j]) for j in range(k)
                 if j in ours and ours[j].status == 0 and np.isfinite(plain_w[j])]
@@ -695,8 +748,11 @@ def run_stream(args, torch, api, inputs):
             "plain_finite": int(np.isfinite(plain_w).sum()),
             "compared": len(both),
             "median_rel_diff": float(np.median(rel)) if rel else None,
-            "kind": "torch matvecs on the factored kernel from the same "
-                    "linear-layout features, stop test every 10 iterations"}
+            "dense_solves": plain_dense, "solves": 3 * k,
+            "kind": "plain Sinkhorn, one problem at a time: dense K = Phi_x Phi_y^T "
+                    "on the device (factored products past 2 GiB) from the same "
+                    "linear-layout features, torch matrix-vector products, stop "
+                    "test every 10 iterations"}
     print(json.dumps(rec), flush=True)
     return 0
 
@@ -735,12 +791,12 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=200_000)
-    ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2006_07057_amd",
-                                                     "tuning_pixels_batch256.json"),
-                    help="pixels_batch256: solver tuning table to load ('none': defaults)")
+    ap.add_argument("--tuning", default=None,
+                    help="solver tuning table to load ('none': defaults; pixels_batch256 "
+                         "loads paper_2006_07057_amd/tuning_pixels_batch256.json unless told)")
     ap.add_argument("--autotune-out", default=None, metavar="PATH",
-                    help="pixels_batch256: tune each class on the batch's own shapes "
-                         "first and store the table at PATH")
+                    help="pixels_batch256 / stream: tune each solver class on the "
+                         "workload's own shapes first and store the table at PATH")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     metavar="GIB", help="only run a plain device-to-device "
                     "copy of this many GiB, three times (the reference "
