@@ -347,12 +347,16 @@ struct LinearDomain {
       __syncthreads();
       return;
     }
+    // registers: every wave needs the whole vector, so it is read from
+    // global memory once per workgroup and handed out through LDS
+    __syncthreads();
+    for (int i = threadIdx.x; i < kR; i += kBlock) lds[i] = i < r ? cld(src + i) : 0.f;
+    __syncthreads();
     const int cl = (threadIdx.x & 63) % G;
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const int col = 4 * cl + 4 * G * c;
-      S.vec[c] = col < r ? cld4(src + col) : f4zero();
-    }
+    for (int c = 0; c < C; ++c)
+      S.vec[c] = *reinterpret_cast<const float4*>(lds + 4 * cl + 4 * G * c);
+    __syncthreads();
   }
   __device__ __forceinline__ static float4 vec_at(const State& S, const float* lds, int c,
                                                   int cl) {
@@ -540,7 +544,7 @@ struct LinearDomain {
       if (split < Sn) {
         for (int b = split; b < g; b += Sn) {
           const float4 v =
-              cld4(slots + (int64_t)cld(members + b) * slot_stride + 4 * col);
+              cld4(slots + (int64_t)members[b] * slot_stride + 4 * col);
           sx.add(v.x); sy.add(v.y); sz.add(v.z); sw.add(v.w);
         }
       }
@@ -640,17 +644,22 @@ struct XRangeDomain {
       __syncthreads();
       return;
     }
+    // registers: every wave needs the whole vector, so it is read from
+    // global memory once per workgroup and handed out through LDS
+    __syncthreads();
+    for (int i = threadIdx.x; i < kR; i += kBlock) {
+      const bool ok = i < r;
+      lds[i] = ok ? cld(src + i) : kNegBig;
+      lds[kR + i] = ok ? cld(src + r + i) : 0.f;
+    }
+    __syncthreads();
     const int cl = (threadIdx.x & 63) % G;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const int col = 4 * cl + 4 * G * c;
-      const bool ok = col < r;
-      const int cc = ok ? col : 0;
-      const float4 e = cld4(src + cc);
-      const float4 m = cld4(src + r + cc);
-      S.vecE[c] = ok ? e : f4fill(kNegBig);
-      S.vecM[c] = ok ? m : f4zero();
+      S.vecE[c] = *reinterpret_cast<const float4*>(lds + 4 * cl + 4 * G * c);
+      S.vecM[c] = *reinterpret_cast<const float4*>(lds + kR + 4 * cl + 4 * G * c);
     }
+    __syncthreads();
   }
 
   // First pass: acc_k += rowM * 2^(rowE + x_k) with a per-column exponent
@@ -985,7 +994,7 @@ struct XRangeDomain {
       CSum fs;   // framed sums: compensated
       if (split < Sn) {
         for (int b = split; b < g; b += Sn) {
-          const float* p = slots + (int64_t)cld(members + b) * slot_stride;
+          const float* p = slots + (int64_t)members[b] * slot_stride;
           if (FRAMED) {
             fs.add(cld(p + col));
           } else {
@@ -1043,6 +1052,10 @@ struct XRangeDomain {
 
 struct Shared {
   double d[kBlock];
+  // the gang's member table (workgroup index of each seat), read once per
+  // solve after the first barrier: the column reductions then find every
+  // partial without a dependent global load
+  int32_t mem[kMaxGroup];
 };
 
 // Reduce a half-step's accumulators into dst (directly when g == 1, else via
@@ -1059,7 +1072,8 @@ template <class Dom, bool FRAMED>
 __device__ __forceinline__ bool finish_half_step(
     const SolveDesc& D, int br, BarrierState& B, typename Dom::State& S,
     float* __restrict__ dst, bool reduce_vec, const float* frame, double& err,
-    int& bad, int& uflow, bool guard_on, int& guard, float* lds, Shared& sh) {
+    int& bad, int& uflow, bool guard_on, int& guard, float* lds, Shared& sh,
+    bool& mem_ready) {
   __shared__ int s_uflow;
   const int g = D.g;
   const double e_blk = block_dsum(err, sh.d);
@@ -1087,13 +1101,18 @@ __device__ __forceinline__ bool finish_half_step(
     if (guard_on) cst(D.dpart + 6 * g + br, g_blk);
   }
   if (!group_barrier(B)) return false;
+  if (!mem_ready) {   // every seat's entry is visible after the barrier
+    for (int i = threadIdx.x; i < g; i += kBlock) sh.mem[i] = cld(D.members + i);
+    __syncthreads();
+    mem_ready = true;
+  }
   if (g > 1) {
     if (guard_on && group_dsum(D.dpart + 6 * g, g, sh.d) > 0.0) {
       guard = 1;
       return true;
     }
     if (reduce_vec)
-      Dom::template column_reduce<FRAMED>(D.slots, D.slot_stride, D.members, g, D.r,
+      Dom::template column_reduce<FRAMED>(D.slots, D.slot_stride, sh.mem, g, D.r,
                                           br, dst, lds, frame, &s_uflow);
     __syncthreads();
     if (FRAMED && threadIdx.x == 0) cst(D.dpart + 5 * g + br, (double)s_uflow);
@@ -1453,6 +1472,7 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
   bool ok = true;
   int uflow = 0;
   int guard = 0;
+  bool mem_ready = false;   // sh.mem holds this gang's member table
   int status = SK_OK;
   // the smallest current marginal a row may have while the r-vector it is
   // summed against has lossy columns (derivation in the loop below):
@@ -1505,7 +1525,7 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
                                              guard, guard_min, lds);
   err = 0.0;
   ok = finish_half_step<Dom, false>(D, br, B, S, uniform_ptr(D.z), true, nullptr, err,
-                                    bad, uflow, false, guard, lds, sh);
+                                    bad, uflow, false, guard, lds, sh, mem_ready);
 
   if (ok && bad) status = SK_ERANGE;
   if (ok) {
@@ -1590,7 +1610,7 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
       // z^(k-1) (from the u-pass of iteration k-1) was lossy: guard the rows
       const bool gv = XR && !ROBUST && lossy;
       ok = finish_half_step<Dom, !ROBUST>(D, br, B, S, wbuf(k), !last, uniform_ptr(D.z), err,
-                                          bad, uflow, gv, guard, lds, sh);
+                                          bad, uflow, gv, guard, lds, sh, mem_ready);
       if (!ok) break;
       if (gv && guard) {
         resume_exit(kResumeU, k - 1);
@@ -1638,7 +1658,7 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
                                                    guard_min, lds);
     }
     ok = finish_half_step<Dom, !ROBUST>(D, br, B, S, uniform_ptr(D.z), true, wbuf(k), err,
-                                        bad, uflow, gu, guard, lds, sh);
+                                        bad, uflow, gu, guard, lds, sh, mem_ready);
     if (!ok) break;
     if (gu && guard) {
       resume_exit(kResumeV, k);
@@ -1720,7 +1740,7 @@ __device__ __forceinline__ void run_solve(const SolveDesc& D, int br, LaunchCtl*
       if (split < Sn) {
         for (int b2 = split; b2 < g; b2 += Sn) {
           const double* ps = reinterpret_cast<const double*>(
-              D.slots + (int64_t)cld(D.members + b2) * D.slot_stride);
+              D.slots + (int64_t)sh.mem[b2] * D.slot_stride);
           sacc += cld(ps + k);
         }
       }
