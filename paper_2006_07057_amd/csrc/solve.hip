@@ -286,32 +286,63 @@ __device__ __forceinline__ bool group_barrier(BarrierState& B) {
   return ok;
 }
 
-// Sum of g float64 values, identical in every workgroup (fixed order).
-__device__ __forceinline__ double group_dsum(const double* __restrict__ src,
-                                             int g, double* lds) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < g; i += kBlock) s += cld(src + i);
-  lds[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = kBlock / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) lds[threadIdx.x] += lds[threadIdx.x + off];
-    __syncthreads();
+// Workgroup sums of float64 values, the same in every thread: a butterfly
+// within each wave (at every step both lanes of a pair add the same two
+// operands, so all lanes end with the same value), then the wave totals
+// added in wave order.  Two sums share the exchange.
+__device__ __forceinline__ void block_dsum2(double& v, double& w, double* lds) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v += __shfl_xor(v, off, 64);
+    w += __shfl_xor(w, off, 64);
   }
-  const double res = lds[0];
+  if ((threadIdx.x & 63) == 0) {
+    lds[threadIdx.x >> 6] = v;
+    lds[kWaves + (threadIdx.x >> 6)] = w;
+  }
+  __syncthreads();
+  v = lds[0];
+  w = lds[kWaves];
+#pragma unroll
+  for (int k = 1; k < kWaves; ++k) {
+    v += lds[k];
+    w += lds[kWaves + k];
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double block_dsum(double v, double* lds) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double res = lds[0];
+#pragma unroll
+  for (int k = 1; k < kWaves; ++k) res += lds[k];
   __syncthreads();
   return res;
 }
 
-__device__ __forceinline__ double block_dsum(double v, double* lds) {
-  lds[threadIdx.x] = v;
-  __syncthreads();
-  for (int off = kBlock / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) lds[threadIdx.x] += lds[threadIdx.x + off];
-    __syncthreads();
+// Sum of g float64 values, identical in every workgroup (fixed order: each
+// thread's strided part, then the workgroup sum above).
+__device__ __forceinline__ double group_dsum(const double* __restrict__ src,
+                                             int g, double* lds) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < g; i += kBlock) s += cld(src + i);
+  return block_dsum(s, lds);
+}
+
+// Two such sums with their loads issued together.
+__device__ __forceinline__ void group_dsum2(const double* __restrict__ a,
+                                            const double* __restrict__ b, int g,
+                                            double* lds, double& sa, double& sb) {
+  sa = 0.0;
+  sb = 0.0;
+  for (int i = threadIdx.x; i < g; i += kBlock) {
+    sa += cld(a + i);
+    sb += cld(b + i);
   }
-  const double res = lds[0];
-  __syncthreads();
-  return res;
+  block_dsum2(sa, sb, lds);
 }
 
 // ================================================================ linear
@@ -1076,8 +1107,8 @@ __device__ __forceinline__ bool finish_half_step(
     bool& mem_ready) {
   __shared__ int s_uflow;
   const int g = D.g;
-  const double e_blk = block_dsum(err, sh.d);
-  const double b_blk = block_dsum((double)bad, sh.d);
+  double e_blk = err, b_blk = (double)bad;
+  block_dsum2(e_blk, b_blk, sh.d);
   const double g_blk = guard_on ? block_dsum((double)guard, sh.d) : 0.0;
   guard = 0;
   if (threadIdx.x == 0) s_uflow = 0;
@@ -1116,8 +1147,9 @@ __device__ __forceinline__ bool finish_half_step(
                                           br, dst, lds, frame, &s_uflow);
     __syncthreads();
     if (FRAMED && threadIdx.x == 0) cst(D.dpart + 5 * g + br, (double)s_uflow);
-    err = group_dsum(D.dpart, g, sh.d);
-    bad = group_dsum(D.dpart + g, g, sh.d) > 0.0 ? 1 : 0;
+    double bsum;
+    group_dsum2(D.dpart, D.dpart + g, g, sh.d, err, bsum);
+    bad = bsum > 0.0 ? 1 : 0;
     if (!group_barrier(B)) return false;
     uflow = (FRAMED && reduce_vec) ? (group_dsum(D.dpart + 5 * g, g, sh.d) > 0.0 ? 1 : 0) : 0;
   } else {
