@@ -227,6 +227,37 @@ __device__ __forceinline__ void cst4(float* p, const float4& v) {
   cst(p + 3, v.w);
 }
 
+// The relaxed atomic loads above stay in program order with the memory
+// operations around them, so a loop that loads an element and stores it to
+// LDS pays one round trip per element.  These helpers issue all of a
+// thread's loads before using any of them.
+
+// K shared vectors of r floats (the k-th at src + k r) into LDS as K blocks
+// of N entries (dst + k N), entries past r set to pad[k].
+template <int N, int K>
+__device__ __forceinline__ void stage_shared(const float* src, int r, float* dst,
+                                             const float (&pad)[K]) {
+  constexpr int kPer = (N + kBlock - 1) / kBlock;
+  float v[K][kPer];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = (int)threadIdx.x + q * kBlock;
+      v[k][q] = i < r ? cld(src + k * r + i) : pad[k];
+    }
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = (int)threadIdx.x + q * kBlock;
+      if (i < N) dst[k * N + i] = v[k][q];
+    }
+}
+
+// slots summed per column in batches of this many workgroup partials
+constexpr int kSlotBatch = 8;
+
 // (E1, M1) + (E2, M2) in the extended-range representation.
 __device__ __forceinline__ void xr_combine(float& E1, float& M1, float E2,
                                            float M2) {
@@ -372,16 +403,17 @@ struct LinearDomain {
   // src: r floats (into LDS, zero-padded to kR, when VL)
   __device__ __forceinline__ static void load_vec(const float* __restrict__ src, int r,
                                   State& S, float* lds) {
+    const float pad[1] = {0.f};
     if (VL) {
       __syncthreads();
-      for (int i = threadIdx.x; i < kR; i += kBlock) lds[i] = i < r ? cld(src + i) : 0.f;
+      stage_shared<kR, 1>(src, r, lds, pad);
       __syncthreads();
       return;
     }
     // registers: every wave needs the whole vector, so it is read from
     // global memory once per workgroup and handed out through LDS
     __syncthreads();
-    for (int i = threadIdx.x; i < kR; i += kBlock) lds[i] = i < r ? cld(src + i) : 0.f;
+    stage_shared<kR, 1>(src, r, lds, pad);
     __syncthreads();
     const int cl = (threadIdx.x & 63) % G;
 #pragma unroll
@@ -573,10 +605,19 @@ struct LinearDomain {
       const int split = t / nc;
       CSum sx, sy, sz, sw;
       if (split < Sn) {
-        for (int b = split; b < g; b += Sn) {
-          const float4 v =
-              cld4(slots + (int64_t)members[b] * slot_stride + 4 * col);
-          sx.add(v.x); sy.add(v.y); sz.add(v.z); sw.add(v.w);
+        for (int b0 = split; b0 < g; b0 += kSlotBatch * Sn) {
+          float4 v[kSlotBatch];
+#pragma unroll
+          for (int q = 0; q < kSlotBatch; ++q) {
+            const int b = b0 + q * Sn;
+            const float* p = slots + (int64_t)members[b < g ? b : 0] * slot_stride;
+            v[q] = b < g ? cld4(p + 4 * col) : f4zero();
+          }
+#pragma unroll
+          for (int q = 0; q < kSlotBatch; ++q)
+            if (b0 + q * Sn < g) {
+              sx.add(v[q].x); sy.add(v[q].y); sz.add(v[q].z); sw.add(v[q].w);
+            }
         }
       }
       // combine the Sn splits: their sums, then their carried errors
@@ -665,24 +706,17 @@ struct XRangeDomain {
   // entry (E = kNegBig, M = 0).
   __device__ __forceinline__ static void load_vec(const float* __restrict__ src, int r,
                                                   State& S, float* lds) {
+    const float pad[2] = {kNegBig, 0.f};
     if (VL) {  // LDS: [E(kR) | M(kR)]
       __syncthreads();
-      for (int i = threadIdx.x; i < kR; i += kBlock) {
-        const bool ok = i < r;
-        lds[i] = ok ? cld(src + i) : kNegBig;
-        lds[kR + i] = ok ? cld(src + r + i) : 0.f;
-      }
+      stage_shared<kR, 2>(src, r, lds, pad);
       __syncthreads();
       return;
     }
     // registers: every wave needs the whole vector, so it is read from
     // global memory once per workgroup and handed out through LDS
     __syncthreads();
-    for (int i = threadIdx.x; i < kR; i += kBlock) {
-      const bool ok = i < r;
-      lds[i] = ok ? cld(src + i) : kNegBig;
-      lds[kR + i] = ok ? cld(src + r + i) : 0.f;
-    }
+    stage_shared<kR, 2>(src, r, lds, pad);
     __syncthreads();
     const int cl = (threadIdx.x & 63) % G;
 #pragma unroll
@@ -1024,13 +1058,24 @@ struct XRangeDomain {
       float e = kNegBig, m = 0.f;
       CSum fs;   // framed sums: compensated
       if (split < Sn) {
-        for (int b = split; b < g; b += Sn) {
-          const float* p = slots + (int64_t)members[b] * slot_stride;
-          if (FRAMED) {
-            fs.add(cld(p + col));
-          } else {
-            xr_combine(e, m, cld(p + col), cld(p + r + col));
+        for (int b0 = split; b0 < g; b0 += kSlotBatch * Sn) {
+          float ve[kSlotBatch], vm[kSlotBatch];
+#pragma unroll
+          for (int q = 0; q < kSlotBatch; ++q) {
+            const int b = b0 + q * Sn;
+            const float* p = slots + (int64_t)members[b < g ? b : 0] * slot_stride;
+            ve[q] = b < g ? cld(p + col) : 0.f;
+            vm[q] = (!FRAMED && b < g) ? cld(p + r + col) : 0.f;
           }
+#pragma unroll
+          for (int q = 0; q < kSlotBatch; ++q)
+            if (b0 + q * Sn < g) {
+              if (FRAMED) {
+                fs.add(ve[q]);
+              } else {
+                xr_combine(e, m, ve[q], vm[q]);
+              }
+            }
         }
       }
       if (FRAMED) {
